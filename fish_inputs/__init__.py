@@ -1,0 +1,260 @@
+"""Seeded synthetic initial states shared by the oracle tests and the HIP path.
+
+This module builds inputs only: it holds none of the arithmetic of the
+operator-split scheme (no fluxes, limiters, sweeps or time steps).  Every
+state is returned as a dict in the layout of the C interface, FP64:
+
+``cell`` (5, nz, ny, nx)   rho, m_x, m_y, m_z, E
+``bx``   (nz, ny, nx+1)    face f between cells f-1 and f along x
+``by``   (nz, ny+1, nx)
+``bz``   (nz+1, ny, nx)
+``phi``  (nz, ny, nx) or None
+
+The magnetic field is always the discrete curl of an edge-centred vector
+potential, so its discrete divergence vanishes up to round-off.  Total energy
+is E = p/(gamma-1) + rho v^2/2 + b_c^2/2 with b_c the mean of the two faces of
+a cell (the energy definition of Sect. 2.1 of the FISH paper).
+
+Recipes (unit box unless stated; x_i = (i + 1/2) dx):
+
+* random-Fourier box: rho = 1 + 0.1 sum_{m=1..8} cos(2 pi k_m.x + theta_m),
+  k_m integer vectors drawn uniformly from 1 <= |k| <= kmax; each velocity
+  component a sum of 8 such modes with N(0,1) amplitudes, scaled to the rms
+  Mach number sqrt(<v^2/c_s^2>); p = 1/gamma uniform; b from a vector
+  potential of 8 modes per component scaled to <b_c^2> = 2 p / beta.
+* stratified sphere: rho = rho_c/(1 + (r/r_c)^2) (1 + 0.01 eta), eta ~ U[-1,1],
+  the matching potential and hydrostatic pressure in closed form (G = 1),
+  v = 0, weak random-potential b with <b_c^2> = 2 <p>/beta; outflow boundaries.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "empty_state", "conserved_from_primitive", "cell_centred_b", "curl_of_potential",
+    "random_fourier_state", "sphere_state", "uniform_state", "kvectors", "batch_box_specs",
+    "serving_requests",
+]
+
+
+def empty_state(nx, ny, nz, with_phi=False):
+    return {
+        "cell": np.zeros((5, nz, ny, nx)),
+        "bx": np.zeros((nz, ny, nx + 1)),
+        "by": np.zeros((nz, ny + 1, nx)),
+        "bz": np.zeros((nz + 1, ny, nx)),
+        "phi": np.zeros((nz, ny, nx)) if with_phi else None,
+    }
+
+
+def cell_centred_b(bx, by, bz):
+    """Mean of the two faces of each cell, per component."""
+    return (0.5 * (bx[:, :, :-1] + bx[:, :, 1:]),
+            0.5 * (by[:, :-1, :] + by[:, 1:, :]),
+            0.5 * (bz[:-1, :, :] + bz[1:, :, :]))
+
+
+def conserved_from_primitive(rho, vx, vy, vz, p, bx, by, bz, gamma, phi=None):
+    """Assemble a state dict from primitive cell fields and face fields."""
+    bcx, bcy, bcz = cell_centred_b(bx, by, bz)
+    E = p / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz) + 0.5 * (bcx * bcx + bcy * bcy + bcz * bcz)
+    cell = np.stack([rho, rho * vx, rho * vy, rho * vz, E]).astype(np.float64)
+    return {"cell": np.ascontiguousarray(cell), "bx": np.ascontiguousarray(bx, dtype=np.float64),
+            "by": np.ascontiguousarray(by, dtype=np.float64), "bz": np.ascontiguousarray(bz, dtype=np.float64),
+            "phi": None if phi is None else np.ascontiguousarray(phi, dtype=np.float64)}
+
+
+def kvectors(kmax, dims=3):
+    """All integer wave vectors with 1 <= |k| <= kmax (Euclidean norm)."""
+    r = np.arange(-kmax, kmax + 1)
+    if dims == 3:
+        kx, ky, kz = np.meshgrid(r, r, r, indexing="ij")
+    else:
+        kx, ky = np.meshgrid(r, r, indexing="ij")
+        kz = np.zeros_like(kx)
+    k = np.stack([kx.ravel(), ky.ravel(), kz.ravel()], axis=1)
+    n2 = (k * k).sum(axis=1)
+    return k[(n2 >= 1) & (n2 <= kmax * kmax)]
+
+
+def _modes(coords, ks, thetas, amps):
+    """sum_m amp_m cos(2 pi k_m . x + theta_m) on the grid given by 1-D coords.
+
+    coords = (x, y, z) 1-D position arrays; result shape (len z, len y, len x).
+    Uses separable complex exponentials (exact up to round-off).
+    """
+    x, y, z = coords
+    out = np.zeros((len(z), len(y), len(x)))
+    for k, th, a in zip(ks, thetas, amps):
+        ex = np.exp(2j * np.pi * k[0] * x)
+        ey = np.exp(2j * np.pi * k[1] * y)
+        ez = np.exp(2j * np.pi * k[2] * z) * (a * np.exp(1j * th))
+        out += (ez[:, None, None] * ey[None, :, None] * ex[None, None, :]).real
+    return out
+
+
+def curl_of_potential(Ax, Ay, Az, dx, dy, dz):
+    """Face fields b = curl A from edge-centred potentials.
+
+    Ax[k, j, i] sits on the x-edge at (x_i, y_{j-1/2}, z_{k-1/2}), shape
+    (nz+1, ny+1, nx); Ay[k, j, i] on (x_{i-1/2}, y_j, z_{k-1/2}), shape
+    (nz+1, ny, nx+1); Az[k, j, i] on (x_{i-1/2}, y_{j-1/2}, z_k), shape
+    (nz, ny+1, nx+1).  Returns bx (nz, ny, nx+1), by (nz, ny+1, nx),
+    bz (nz+1, ny, nx), whose discrete divergence is zero up to round-off.
+    """
+    bx = (Az[:, 1:, :] - Az[:, :-1, :]) / dy - (Ay[1:, :, :] - Ay[:-1, :, :]) / dz
+    by = (Ax[1:, :, :] - Ax[:-1, :, :]) / dz - (Az[:, :, 1:] - Az[:, :, :-1]) / dx
+    bz = (Ay[:, :, 1:] - Ay[:, :, :-1]) / dx - (Ax[:, 1:, :] - Ax[:, :-1, :]) / dy
+    return bx, by, bz
+
+
+def _potential_field(rng, n, L, kmax, nmodes, periodic):
+    """Random edge-centred vector potential -> face field (unscaled)."""
+    nx, ny, nz = n
+    Lx, Ly, Lz = L
+    dx, dy, dz = Lx / nx, Ly / ny, Lz / nz
+    kset = kvectors(kmax)
+    cen = [(np.arange(m) + 0.5) * d for m, d in zip(n, (dx, dy, dz))]       # cell centres
+    lo = [np.arange(m + 1) * d for m, d in zip(n, (dx, dy, dz))]            # low faces 0..n
+    comps = []
+    for _ in range(3):
+        idx = rng.integers(0, len(kset), size=nmodes)
+        th = rng.uniform(0.0, 2.0 * np.pi, size=nmodes)
+        amp = rng.standard_normal(nmodes)
+        # wave vectors in units of the box: k / L per axis
+        comps.append((kset[idx], th, amp))
+
+    def evaluate(comp, coords):
+        ks, th, amp = comp
+        kk = ks.astype(np.float64) / np.array([Lx, Ly, Lz])
+        return _modes(coords, kk, th, amp)
+
+    Ax = evaluate(comps[0], (cen[0], lo[1], lo[2]))
+    Ay = evaluate(comps[1], (lo[0], cen[1], lo[2]))
+    Az = evaluate(comps[2], (lo[0], lo[1], cen[2]))
+    if periodic:
+        # exact periodic images: index n along a face axis equals index 0
+        Ax[:, -1, :] = Ax[:, 0, :]
+        Ax[-1, :, :] = Ax[0, :, :]
+        Ay[:, :, -1] = Ay[:, :, 0]
+        Ay[-1, :, :] = Ay[0, :, :]
+        Az[:, :, -1] = Az[:, :, 0]
+        Az[:, -1, :] = Az[:, 0, :]
+    return curl_of_potential(Ax, Ay, Az, dx, dy, dz)
+
+
+def random_fourier_state(n, seed, mach=0.5, beta=10.0, kmax=4, gamma=5.0 / 3.0, nmodes=8, L=(1.0, 1.0, 1.0)):
+    """Periodic random-Fourier box (smooth, shock-forming at high Mach)."""
+    if np.isscalar(n):
+        n = (int(n),) * 3
+    nx, ny, nz = n
+    rng = np.random.Generator(np.random.PCG64(seed))
+    kset = kvectors(kmax)
+    cen = [(np.arange(m) + 0.5) * (l / m) for m, l in zip(n, L)]
+    scale = np.array(L, dtype=np.float64)
+
+    idx = rng.integers(0, len(kset), size=nmodes)
+    th = rng.uniform(0.0, 2.0 * np.pi, size=nmodes)
+    rho = 1.0 + 0.1 * _modes(cen, kset[idx] / scale, th, np.ones(nmodes))
+
+    vel = []
+    for _ in range(3):
+        idx = rng.integers(0, len(kset), size=nmodes)
+        th = rng.uniform(0.0, 2.0 * np.pi, size=nmodes)
+        amp = rng.standard_normal(nmodes)
+        vel.append(_modes(cen, kset[idx] / scale, th, amp))
+    p0 = 1.0 / gamma
+    p = np.full((nz, ny, nx), p0)
+    cs2 = gamma * p / rho
+    msq = np.mean((vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2) / cs2)
+    vs = mach / math.sqrt(msq) if msq > 0 else 0.0
+    vx, vy, vz = (v * vs for v in vel)
+
+    bx, by, bz = _potential_field(rng, n, L, kmax, nmodes, periodic=True)
+    bcx, bcy, bcz = cell_centred_b(bx, by, bz)
+    b2 = np.mean(bcx ** 2 + bcy ** 2 + bcz ** 2)
+    bs = math.sqrt(2.0 * p0 / beta / b2) if (beta > 0 and b2 > 0) else 0.0
+    return conserved_from_primitive(rho, vx, vy, vz, p, bx * bs, by * bs, bz * bs, gamma)
+
+
+def sphere_state(n, seed, gamma=5.0 / 3.0, rho_c=1.0, r_c=0.1, beta=100.0, kmax=4, nmodes=8, noise=0.01):
+    """Stratified sphere in a fixed potential, for outflow boundaries (G = 1).
+
+    rho = rho_c/(1+x^2), x = r/r_c; enclosed-mass potential
+    phi = 4 pi rho_c r_c^2 (atan(x)/x + ln(1+x^2)/2) solves lap phi = 4 pi rho;
+    p = 4 pi rho_c^2 r_c^2 (pi^2/8 - atan(x)/x - atan(x)^2/2) solves
+    dp/dr = -rho dphi/dr with p -> 0 at infinity.
+    """
+    if np.isscalar(n):
+        n = (int(n),) * 3
+    nx, ny, nz = n
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = (np.arange(nx) + 0.5) / nx - 0.5
+    y = (np.arange(ny) + 0.5) / ny - 0.5
+    z = (np.arange(nz) + 0.5) / nz - 0.5
+    r = np.sqrt(z[:, None, None] ** 2 + y[None, :, None] ** 2 + x[None, None, :] ** 2)
+    s = r / r_c
+    small = s < 1e-6
+    s_safe = np.where(small, 1.0, s)
+    atan_over = np.where(small, 1.0 - s * s / 3.0, np.arctan(s_safe) / s_safe)
+    K = 4.0 * math.pi * rho_c * r_c * r_c
+    phi = K * (atan_over + 0.5 * np.log1p(s * s))
+    p = K * rho_c * (math.pi ** 2 / 8.0 - atan_over - 0.5 * np.arctan(s) ** 2)
+    eta = rng.uniform(-1.0, 1.0, size=(nz, ny, nx))
+    rho = rho_c / (1.0 + s * s) * (1.0 + noise * eta)
+    zero = np.zeros_like(rho)
+    bx, by, bz = _potential_field(rng, n, (1.0, 1.0, 1.0), kmax, nmodes, periodic=False)
+    bcx, bcy, bcz = cell_centred_b(bx, by, bz)
+    b2 = np.mean(bcx ** 2 + bcy ** 2 + bcz ** 2)
+    bs = math.sqrt(2.0 * float(np.mean(p)) / beta / b2)
+    return conserved_from_primitive(rho, zero, zero, zero, p, bx * bs, by * bs, bz * bs, gamma, phi=phi)
+
+
+def uniform_state(n, rho=1.0, v=(0.0, 0.0, 0.0), p=1.0, b=(0.0, 0.0, 0.0), gamma=5.0 / 3.0):
+    nx, ny, nz = n
+    one = np.ones((nz, ny, nx))
+    bx = np.full((nz, ny, nx + 1), float(b[0]))
+    by = np.full((nz, ny + 1, nx), float(b[1]))
+    bz = np.full((nz + 1, ny, nx), float(b[2]))
+    return conserved_from_primitive(rho * one, v[0] * one, v[1] * one, v[2] * one, p * one, bx, by, bz, gamma)
+
+
+# Edge lengths of the batched many-box workload (geometric set 16..64).
+BATCH_EDGES = (16, 24, 32, 48, 64)
+
+
+def batch_box_specs(nboxes, base_seed=1000, edges=BATCH_EDGES, seed=0):
+    """Per-box (edge, seed, mach, beta) of the batched workload.
+
+    Edge drawn uniformly from the geometric set (log-uniform), Mach from
+    U[0.3, 2], beta log-uniform on [0.5, 50]; box b uses seed base_seed + b.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for b in range(nboxes):
+        e = int(edges[rng.integers(0, len(edges))])
+        mach = float(rng.uniform(0.3, 2.0))
+        beta = float(math.exp(rng.uniform(math.log(0.5), math.log(50.0))))
+        out.append({"edge": e, "seed": base_seed + b, "mach": mach, "beta": beta})
+    return out
+
+
+def serving_requests(nreq, rate, seed=7, edge_range=(32, 192), step_range=(10, 200)):
+    """Poisson-arrival request stream: (arrival time, edge, steps, seed).
+
+    Inter-arrival times are exponential with the given rate (requests per
+    second); edges log-uniform on edge_range (rounded to an integer), step
+    counts uniform on step_range (inclusive).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    lo, hi = math.log(edge_range[0]), math.log(edge_range[1])
+    for r in range(nreq):
+        t += float(rng.exponential(1.0 / rate))
+        edge = int(round(math.exp(rng.uniform(lo, hi))))
+        steps = int(rng.integers(step_range[0], step_range[1] + 1))
+        out.append({"arrival": t, "edge": edge, "steps": steps, "seed": 100000 + r})
+    return out

@@ -1,0 +1,128 @@
+"""Oracle pins: gravity source and hydrostatic-gradient subtraction (CPU only).
+
+* a uniform state at rest in a linear potential: one fluid sweep gives the
+  closed-form kick of the unsplit predictor/corrector (Eqs. 41-43) -- this
+  fixes the sign and the size of the source;
+* HSE (i): with a constant potential and a uniform velocity the HSE flux
+  equals the plain relaxed flux (Eqs. 54-57 reduce to Eqs. 24-25);
+* HSE (ii): on a discretely hydrostatic pencil (u_i+1 - u_i = g_i, Eq. 51)
+  the acoustic dissipation vanishes, so the predictor no longer depends on its
+  dissipation scale;
+* HSE (iii): the stratified sphere drifts less with the subtraction on.
+"""
+import numpy as np
+import pytest
+from scipy import optimize
+
+import analytic as an
+import fish_inputs as fi
+from oracle import OUTFLOW, Oracle
+
+GAMMA = 5.0 / 3.0
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("hse", [False, True])
+def test_linear_potential_kick_closed_form(axis, hse):
+    n = [1, 1, 1]
+    n[axis] = 12
+    rho, p, g, dt = 1.3, 0.8, 0.7, 0.01
+    st = fi.uniform_state(n, rho=rho, p=p, b=(0.2, 0.1, 0.3), gamma=GAMMA)
+    phi = g * an.centres(12)
+    shape = [1, 1, 1]
+    shape[2 - axis] = 12
+    st["phi"] = np.broadcast_to(phi.reshape(shape), (n[2], n[1], n[0])).copy()
+    o = Oracle(*n, bc=(OUTFLOW,) * 3, gravity=True, hse=hse, gamma=GAMMA)
+    o.set_state(st)
+    o.apply("L", axis, dt)
+    out = o.get_state()
+    m = out["cell"][1 + axis].reshape(-1)
+    E = out["cell"][4].reshape(-1)
+    np.testing.assert_allclose(m, -rho * g * dt, rtol=1e-12)
+    np.testing.assert_allclose(E, st["cell"][4].reshape(-1) + 0.5 * rho * (g * dt) ** 2, rtol=1e-13)
+    np.testing.assert_array_equal(out["cell"][0], st["cell"][0])
+
+
+def test_hse_reduces_to_plain_flux_for_constant_potential():
+    """Uniform v, p and b with varying rho (an entropy wave): the velocity stays
+    uniform through the predictor, so max|v| + max c_F = max(|v| + c_F) at every
+    interface of both stages and the HSE flux equals the plain one."""
+    n = 24
+    rng = np.random.default_rng(4)
+    x = an.centres(n)
+    rho = 1.0 + 0.3 * np.sin(2 * np.pi * x) + 0.05 * rng.standard_normal(n)
+    p = 0.8 * np.ones(n)
+    v = [0.35 * np.ones(n), 0.1 * np.ones(n), -0.2 * np.ones(n)]
+    bt = [0.3 * np.ones(n), 0.2 * np.ones(n)]
+    st = an.state_1d(0, n, rho, v, p, bt, GAMMA, b_normal=0.4)
+    st["phi"] = np.full((1, 1, n), 3.0)
+    res = []
+    for hse in (False, True):
+        o = Oracle(n, 1, 1, gravity=True, hse=hse, gamma=GAMMA)
+        o.set_state(st)
+        o.apply("L", 0, 0.4 * o.cfl_dt())
+        res.append(o.get_state()["cell"])
+    assert np.max(np.abs(res[0] - res[1])) <= 1e-13 * np.max(np.abs(res[0]))
+    assert np.max(np.abs(res[0] - st["cell"])) > 1e-3
+
+
+def _hydrostatic_pencil(n, dphi, rho0=1.0, p0=1.0):
+    """v = 0, b = 0 pencil with u_i+1 - u_i = g_i exactly (Eq. 51) for rho and E.
+
+    Solved cell by cell with a root finder from the HSE gradient definition:
+    g = (xi_i + xi_i+1)/2 (phi_i+1 - phi_i)/(c_i c_i+1), xi = -(rho, m, E + p).
+    """
+    rho, p = [rho0], [p0]
+    for i in range(n - 1):
+        r0, q0 = rho[-1], p[-1]
+        c0 = np.sqrt(GAMMA * q0 / r0)
+        E0 = q0 / (GAMMA - 1)
+
+        def res(z):
+            r1, q1 = z
+            c1 = np.sqrt(GAMMA * q1 / r1)
+            E1 = q1 / (GAMMA - 1)
+            f = dphi / (c0 * c1)
+            return [r1 - r0 + 0.5 * (r0 + r1) * f, E1 - E0 + 0.5 * (E0 + q0 + E1 + q1) * f]
+
+        sol = optimize.fsolve(res, [r0, q0], xtol=1e-13)
+        rho.append(sol[0])
+        p.append(sol[1])
+    return np.array(rho), np.array(p)
+
+
+def test_hse_removes_acoustic_dissipation_on_discrete_equilibrium():
+    n = 32
+    h = 1.0 / n
+    gacc = 2.0
+    rho, p = _hydrostatic_pencil(n, gacc * h)
+    zero = np.zeros(n)
+    st = an.state_1d(0, n, rho, [zero, zero, zero], p, [zero, zero], GAMMA)
+    st["phi"] = (gacc * an.centres(n)).reshape(1, 1, n)
+    inner = slice(4, n - 4)  # away from the outflow ghosts
+    spread = {}
+    for hse in (False, True):
+        outs = []
+        for alpha in (0.0, 1.0):
+            o = Oracle(n, 1, 1, bc=(OUTFLOW,) * 3, gravity=True, hse=hse, predictor_alpha=alpha, gamma=GAMMA)
+            o.set_state(st)
+            o.apply("L", 0, 0.5 * o.cfl_dt())
+            outs.append(o.get_state()["cell"][:, 0, 0, inner])
+        spread[hse] = np.max(np.abs(outs[1] - outs[0])) / np.max(np.abs(outs[0]))
+    assert spread[True] <= 1e-14, spread
+    assert spread[False] >= 1e-9, spread
+
+
+def test_hse_sphere_drifts_less():
+    n = 32
+    st = fi.sphere_state(n, 0)
+    vmax = {}
+    for hse in (False, True):
+        o = Oracle(n, n, n, bc=(OUTFLOW,) * 3, gravity=True, hse=hse, cfl=0.5)
+        o.set_state(st)
+        for _ in range(20):
+            o.strang_step(o.cfl_dt())
+        x = o.get_state()
+        v = np.sqrt(x["cell"][1] ** 2 + x["cell"][2] ** 2 + x["cell"][3] ** 2) / x["cell"][0]
+        vmax[hse] = v.max()
+    assert vmax[True] < vmax[False], vmax
