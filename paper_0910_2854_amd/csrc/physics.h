@@ -1,0 +1,153 @@
+// physics.h -- per-cell and per-interface arithmetic of the FISH sweeps,
+// as device functions for gfx950.  Templated on the storage/arithmetic type T
+// (double, or float with FP64 pressure recovery) and on the sweep axis D so
+// that every component index is a compile-time constant (no scratch).
+//
+// Sect. 2.1-2.4 of the FISH paper; equation numbers are the printed ones.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fish {
+
+enum { RHO = 0, MX = 1, MY = 2, MZ = 3, EN = 4 };
+
+// Quantities of one cell for a sweep along D (Sect. 2.2).  F is the flux of
+// Eq. (17) with x replaced by D, d the freezing speed |v_D| + c_F of Eq. (21).
+// cS and xiE (= -(E + p), the energy entry of Eq. 50) only for HSE.
+template <typename T>
+struct CellQ {
+  T u[5];
+  T F[5];
+  T vd, cF, d;
+  T cS, xiE;
+};
+
+// Pressure from total energy, E = rho e + m^2/(2 rho) + b^2/2, p = (gamma-1) rho e
+// (Sect. 2.1, Eq. 5).  The cancellation step: always evaluated in FP64.
+__device__ __forceinline__ double pressure_fp64(double rho, double mx, double my, double mz, double E,
+                                                double bx, double by, double bz, double gamma,
+                                                double* b2_out) {
+  const double b2 = bx * bx + by * by + bz * bz;
+  const double m2 = mx * mx + my * my + mz * mz;
+  *b2_out = b2;
+  return (gamma - 1.0) * (E - 0.5 * m2 / rho - 0.5 * b2);
+}
+
+template <typename T, int D, bool HSE>
+__device__ __forceinline__ void cell_quantities(const T* u, const T* b, double gamma, CellQ<T>& c) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) c.u[k] = u[k];
+  const T rho = u[RHO];
+  const T v0 = u[MX] / rho, v1 = u[MY] / rho, v2 = u[MZ] / rho;
+  const T v[3] = {v0, v1, v2};
+  double b2d;
+  const double pd = pressure_fp64((double)rho, (double)u[MX], (double)u[MY], (double)u[MZ], (double)u[EN],
+                                  (double)b[0], (double)b[1], (double)b[2], gamma, &b2d);
+  const T p = (T)pd;
+  const T b2 = (T)b2d;
+  const T ptot = p + T(0.5) * b2;
+  const T bv = b[0] * v0 + b[1] * v1 + b[2] * v2;
+  // Directional fast magnetosonic speed (named after Eq. 21).
+  const T a2 = (T)gamma * p / rho;
+  const T q = a2 + b2 / rho;
+  const T disc = q * q - T(4) * a2 * b[D] * b[D] / rho;
+  const T cf = sqrt(T(0.5) * (q + sqrt(disc < T(0) ? T(0) : disc)));
+  const T md = u[MX + D];
+  c.F[RHO] = md;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T f = md * v[k] - b[D] * b[k];
+    if (k == D) f += ptot;
+    c.F[MX + k] = f;
+  }
+  c.F[EN] = (u[EN] + ptot) * v[D] - b[D] * bv;
+  c.vd = v[D];
+  c.cF = cf;
+  c.d = fabs(v[D]) + cf;
+  if (HSE) {
+    c.cS = sqrt(a2);
+    c.xiE = -(u[EN] + p);
+  } else {
+    c.cS = T(0);
+    c.xiE = T(0);
+  }
+}
+
+// Limiters, Eqs. (29)-(30).  van Leer as the harmonic mean 2ab/(a+b) where a
+// and b share a sign (the printed sign prefactor would flip negative pairs).
+template <typename T>
+__device__ __forceinline__ T minmod(T a, T b) {
+  if (a * b <= T(0)) return T(0);
+  return a > T(0) ? (a < b ? a : b) : (a > b ? a : b);
+}
+template <typename T>
+__device__ __forceinline__ T vanleer(T a, T b) {
+  if (a * b <= T(0)) return T(0);
+  return T(2) * a * b / (a + b);
+}
+template <typename T>
+__device__ __forceinline__ T limit(T a, T b, int limiter) {
+  return limiter == 0 ? minmod(a, b) : vanleer(a, b);
+}
+
+// Dissipation Q_j at the interface between cells L and R, so that the
+// first-order relaxed flux is (F_L + F_R)/2 - Q_j/2:
+//   no HSE: Q = max(d_L, d_R) (u_R - u_L), Eqs. (24)-(25);
+//   HSE:    Q = max(|v_L|, |v_R|) du + max(cF_L, cF_R) minmod(du - g, du),
+//           g = (xi_L + xi_R)/2 (phi_R - phi_L)/(cS_L cS_R), Eqs. (50)-(57).
+template <typename T, bool HSE>
+__device__ __forceinline__ void dissipation(const CellQ<T>& L, const CellQ<T>& R, T phiL, T phiR, T* Q) {
+  if (!HSE) {
+    const T dmax = L.d > R.d ? L.d : R.d;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Q[k] = dmax * (R.u[k] - L.u[k]);
+  } else {
+    const T avL = fabs(L.vd), avR = fabs(R.vd);
+    const T dadv = avL > avR ? avL : avR;
+    const T dac = L.cF > R.cF ? L.cF : R.cF;
+    const T scale = (phiR - phiL) / (L.cS * R.cS);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const T du = R.u[k] - L.u[k];
+      const T xiL = (k == EN) ? L.xiE : -L.u[k];
+      const T xiR = (k == EN) ? R.xiE : -R.u[k];
+      const T g = T(0.5) * (xiL + xiR) * scale;
+      const T delta = minmod(du - g, du);
+      Q[k] = dadv * du + dac * delta;
+    }
+  }
+}
+
+// Unsplit gravitational source of cell i, Eq. (42) with the sign of Eq. (36):
+// S = -(0, rho e_D, m_D) (phi_i+1 - phi_i-1)/(2 h).
+template <typename T, int D>
+__device__ __forceinline__ void gravity_source(T rho, T mD, T dphi2, T h, T* S) {
+  const T gr = dphi2 / (T(2) * h);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) S[k] = T(0);
+  S[MX + D] = -rho * gr;
+  S[EN] = -mD * gr;
+}
+
+// ----------------------------------------------------------- index maps
+// Periodic axes wrap; outflow axes copy the nearest real entry (zeroth-order
+// extrapolation).  A face array along its own normal has n+1 real faces on
+// an outflow axis (last real face n) and n on a periodic one.
+__device__ __forceinline__ int wrap(int i, int n) {
+  if (i >= 0 && i < n) return i;
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+__device__ __forceinline__ int map_cell(int i, int n, int bc) {
+  if (i >= 0 && i < n) return i;
+  if (bc == 0) return wrap(i, n);
+  return i < 0 ? 0 : n - 1;
+}
+__device__ __forceinline__ int map_face(int i, int n, int bc) {
+  if (bc == 0) return wrap(i, n);
+  return i < 0 ? 0 : (i > n ? n : i);
+}
+
+}  // namespace fish

@@ -1,0 +1,229 @@
+"""GPU parity: the HIP library (through its C interface) against the FP64 oracle.
+
+Every case prints what it runs before touching the GPU.  Tolerances:
+FP64 per-sub-operator max relative error <= 1e-12; FP64 full steps per-field
+relative L1 <= 1e-10 after 10 steps; FP32 storage with FP64 pressure
+recovery per-field relative L1 <= 1e-5 after 10 steps on smooth data.
+"""
+import numpy as np
+import pytest
+
+try:  # first torch import on a fresh machine is slow: keep it out of the timed tests
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover
+    torch = None
+
+import fish_inputs as fi
+from oracle import OUTFLOW, PERIODIC, Oracle
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("cell", "bx", "by", "bz")
+
+
+def _box(n, **kw):
+    import paper_0910_2854_amd as fish
+    return fish.Box(*n, **kw)
+
+
+def rel_l1(a, b):
+    den = np.sum(np.abs(b))
+    return float(np.sum(np.abs(a - b)) / den) if den > 0 else float(np.sum(np.abs(a - b)))
+
+
+def per_field_rel_l1(sg, so):
+    out = {}
+    for k in range(5):
+        out[("rho", "mx", "my", "mz", "E")[k]] = rel_l1(sg["cell"][k], so["cell"][k])
+    for k in ("bx", "by", "bz"):
+        out[k] = rel_l1(sg[k], so[k])
+    return out
+
+
+def max_rel(sg, so):
+    worst = 0.0
+    for k in FIELDS:
+        scale = np.max(np.abs(so[k])) + 1e-300
+        worst = max(worst, float(np.max(np.abs(sg[k] - so[k])) / scale))
+    return worst
+
+
+CASES = [
+    # (shape, bc, gravity, hse, seed)
+    ((12, 10, 8), (PERIODIC,) * 3, False, False, 1),
+    ((9, 70, 5), (PERIODIC,) * 3, False, False, 2),       # two segments + ragged tail along y
+    ((6, 5, 131), (PERIODIC,) * 3, False, False, 3),       # three segments along z
+    ((11, 7, 6), (OUTFLOW,) * 3, False, False, 4),
+    ((10, 9, 8), (OUTFLOW, PERIODIC, OUTFLOW), True, False, 5),
+    ((10, 9, 8), (OUTFLOW,) * 3, True, True, 6),
+    ((16, 1, 1), (PERIODIC,) * 3, False, False, 7),        # inactive axes
+    ((1, 13, 3), (PERIODIC, OUTFLOW, PERIODIC), False, False, 8),
+    ((2, 3, 2), (PERIODIC,) * 3, False, False, 9),          # wrap more than once
+]
+
+
+def _state(n, bc, gravity, seed):
+    if gravity:
+        st = fi.sphere_state(n, seed)
+        if any(b == PERIODIC for b in bc):
+            # keep the sphere, periodic face n = face 0 is ignored on input
+            pass
+        return st
+    return fi.random_fourier_state(n, seed=seed, mach=0.8, beta=2.0, kmax=2)
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("op", ["L", "B"])
+def test_suboperator_parity_fp64(case, op):
+    n, bc, grav, hse, seed = CASES[case]
+    st = _state(n, bc, grav, seed)
+    kw = dict(bc=bc, gravity=grav, hse=hse)
+    o = Oracle(*n, **kw)
+    o.set_state(st)
+    dt = 0.4 * o.cfl_dt()
+    for d in range(3):
+        print(f"sub-operator {op}{d} case {case} shape {n} bc {bc} grav {grav} hse {hse}", flush=True)
+        o2 = Oracle(*n, **kw)
+        o2.set_state(st)
+        o2.apply(op, d, dt)
+        ref = o2.get_state(check=False)
+        g = _box(n, precision="fp64", **kw)
+        g.set_state(st)
+        g.sweep(op, d, dt)
+        out = g.get_state(check=False)
+        g.close()
+        err = max_rel(out, ref)
+        assert err <= 1e-12, (op, d, err)
+
+
+def _run_pair(n, st, steps, precision, **kw):
+    o = Oracle(*n, **kw)
+    o.set_state(st)
+    g = _box(n, precision=precision, **kw)
+    g.set_state(st)
+    for _ in range(steps):
+        dt = o.cfl_dt()
+        o.strang_step(dt)
+        g.strang_step(dt)
+    return g, o
+
+
+def test_c1_ten_steps_fp64():
+    """32^3 periodic random-Fourier box (rms Mach 0.5, beta 10), 10 steps."""
+    print("C1 32^3 fp64 10 steps", flush=True)
+    st = fi.random_fourier_state(32, seed=0, mach=0.5, beta=10.0, kmax=4)
+    g, o = _run_pair((32, 32, 32), st, 10, "fp64", cfl=0.5)
+    errs = per_field_rel_l1(g.get_state(), o.get_state())
+    print(errs)
+    assert max(errs.values()) <= 1e-10, errs
+
+
+def test_c1_ten_steps_fp32():
+    print("C1 32^3 fp32 10 steps", flush=True)
+    st = fi.random_fourier_state(32, seed=0, mach=0.5, beta=10.0, kmax=4)
+    g, o = _run_pair((32, 32, 32), st, 10, "fp32", cfl=0.5)
+    errs = per_field_rel_l1(g.get_state(), o.get_state())
+    print(errs)
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_sphere_outflow_hse_fp64_steps():
+    print("sphere 24^3 outflow gravity hse fp64 3 steps", flush=True)
+    n = (24, 24, 24)
+    st = fi.sphere_state(n, 0)
+    kw = dict(bc=(OUTFLOW,) * 3, gravity=True, hse=True, cfl=0.5)
+    g, o = _run_pair(n, st, 3, "fp64", **kw)
+    errs = per_field_rel_l1(g.get_state(), o.get_state())
+    print(errs)
+    assert max(errs.values()) <= 1e-10, errs
+
+
+def test_device_cfl_matches_oracle():
+    print("CFL 20^3 fp64 and fp32", flush=True)
+    st = fi.random_fourier_state((20, 18, 16), seed=11, mach=1.0, beta=1.0, kmax=3)
+    o = Oracle(20, 18, 16)
+    o.set_state(st)
+    ref = o.cfl_dt()
+    for prec, tol in (("fp64", 1e-14), ("fp32", 1e-6)):
+        g = _box((20, 18, 16), precision=prec)
+        g.set_state(st)
+        assert abs(g.cfl_dt() - ref) <= tol * ref, prec
+        g.close()
+
+
+def test_device_resident_dt_step_matches_oracle():
+    """fish_strang_step(0): the device takes the CFL step itself."""
+    print("dt==0 steps 16^3 fp64", flush=True)
+    st = fi.random_fourier_state(16, seed=12, mach=0.5, beta=5.0, kmax=3)
+    o = Oracle(16, 16, 16)
+    o.set_state(st)
+    g = _box((16, 16, 16), precision="fp64")
+    g.set_state(st)
+    for _ in range(3):
+        o.strang_step(0.0)
+        g.strang_step(0.0)
+    so, sg = o.get_state(), g.get_state()
+    assert abs(sg["t"] - so["t"]) <= 1e-13 * so["t"]
+    assert max(per_field_rel_l1(sg, so).values()) <= 1e-11
+
+
+def test_gpu_conservation_and_divergence():
+    print("conservation 24^3 fp64", flush=True)
+    st = fi.random_fourier_state(24, seed=13, mach=0.5, beta=10.0, kmax=3)
+    g = _box((24, 24, 24), precision="fp64")
+    g.set_state(st)
+    d0 = g.diagnostics()
+    for _ in range(5):
+        g.strang_step(0.0)
+    d1 = g.diagnostics()
+    assert abs(d1["mass"] - d0["mass"]) <= 1e-13 * d0["mass"]
+    assert abs(d1["energy"] - d0["energy"]) <= 1e-13 * d0["energy"]
+    assert d1["divb_max"] * (1 / 24) / d1["bmax"] <= 1e-12
+    o = Oracle(24, 24, 24)
+    o.set_state(st)
+    od = o.diagnostics()
+    assert abs(od["mass"] - d0["mass"]) <= 1e-14 * od["mass"]
+    assert np.allclose(od["flux"], d0["flux"], rtol=0, atol=1e-14)
+
+
+def test_gpu_determinism_bitwise():
+    print("determinism 20^3 fp32", flush=True)
+    st = fi.random_fourier_state(20, seed=14, mach=0.5, beta=3.0, kmax=3)
+    outs = []
+    for _ in range(2):
+        g = _box((20, 20, 20), precision="fp32")
+        g.set_state(st)
+        for _ in range(3):
+            g.strang_step(0.0)
+        outs.append(g.get_state())
+        g.close()
+    for k in FIELDS:
+        assert np.array_equal(outs[0][k], outs[1][k])
+
+
+def test_gpu_uniform_state_bitwise():
+    print("uniform 9x7x5 outflow fp32/fp64", flush=True)
+    n = (9, 7, 5)
+    st = fi.uniform_state(n, rho=1.3, v=(0.3, -0.2, 0.1), p=0.7, b=(0.4, -0.5, 0.25))
+    for prec in ("fp64", "fp32"):
+        for bc in ((PERIODIC,) * 3, (OUTFLOW,) * 3):
+            g = _box(n, precision=prec, bc=bc)
+            g.set_state(st)
+            ref = g.get_state()
+            for _ in range(2):
+                g.strang_step(0.0)
+            out = g.get_state()
+            for k in FIELDS:
+                assert np.array_equal(out[k], ref[k]), (prec, bc, k)
+            g.close()
+
+
+def test_gpu_rejects_bad_state():
+    import paper_0910_2854_amd as fish
+    print("bad state 4^3", flush=True)
+    st = fi.uniform_state((4, 4, 4), p=0.5)
+    st["cell"][4, 1, 2, 3] = -1.0
+    g = _box((4, 4, 4))
+    with pytest.raises(fish.FishError) as e:
+        g.set_state(st)
+    assert e.value.code == fish.FISH_ERR_STATE
