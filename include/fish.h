@@ -130,6 +130,23 @@ int fish_diagnostics(fish_ctx* ctx, double* out10);
 /* Bytes of device memory the context holds (state, double buffers, scratch). */
 size_t fish_device_bytes(const fish_ctx* ctx);
 
+/* Kernel classes for the timing hook below. */
+enum {
+  FISH_KERNEL_FLUID = 1,       /* fluid sweep L_d                          */
+  FISH_KERNEL_ADVECT = 2,      /* field advection of B_d (edge fluxes)     */
+  FISH_KERNEL_CONSTRAINT = 4,  /* constraint update of B_d                 */
+  FISH_KERNEL_CHECK = 8        /* CFL reduction and state check            */
+};
+
+/* Measurement hook (not part of the scheme): while enabled, every launch of a
+ * kernel class in `mask` is bracketed by two hipEvents recorded on the
+ * context's stream (at most max_launches launches are recorded).  mask == 0
+ * disables it.  fish_timing_read synchronises the stream, returns the number
+ * of recorded launches and their summed duration in milliseconds, and clears
+ * the record. */
+int fish_timing_enable(fish_ctx* ctx, int mask, int max_launches);
+int fish_timing_read(fish_ctx* ctx, int* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,7 +53,9 @@ class FishError(RuntimeError):
 
 
 EXPORTS = ("fish_create", "fish_destroy", "fish_last_error", "fish_set_state", "fish_get_state",
-           "fish_cfl_dt", "fish_strang_step", "fish_sweep", "fish_diagnostics", "fish_device_bytes")
+           "fish_cfl_dt", "fish_strang_step", "fish_sweep", "fish_diagnostics", "fish_device_bytes",
+           "fish_timing_enable", "fish_timing_read")
+KERNEL_FLUID, KERNEL_ADVECT, KERNEL_CONSTRAINT, KERNEL_CHECK = 1, 2, 4, 8
 
 _lib = None
 
@@ -80,8 +82,10 @@ def load_library(path: str = LIB_PATH):
     lib.fish_diagnostics.argtypes = [vp, P(d)]
     lib.fish_device_bytes.argtypes = [vp]
     lib.fish_device_bytes.restype = ctypes.c_size_t
+    lib.fish_timing_enable.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    lib.fish_timing_read.argtypes = [vp, P(ctypes.c_int), P(d)]
     for name in ("fish_create", "fish_set_state", "fish_get_state", "fish_cfl_dt", "fish_strang_step",
-                 "fish_sweep", "fish_diagnostics"):
+                 "fish_sweep", "fish_diagnostics", "fish_timing_enable", "fish_timing_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -212,6 +216,17 @@ class Box:
         """One sub-operator: op 'L' (fluid) or 'B' (field), direction 0/1/2."""
         code = {"L": 0, "B": 1}[op] if isinstance(op, str) else int(op)
         self._check(self._lib.fish_sweep(self._h, code, int(direction), float(dt)))
+
+    def timing_enable(self, mask, max_launches=4096):
+        """Record hipEvents around launches of the kernel classes in mask."""
+        self._check(self._lib.fish_timing_enable(self._h, int(mask), int(max_launches)))
+
+    def timing_read(self):
+        """(launches, total milliseconds) recorded since the last read."""
+        n = ctypes.c_int()
+        ms = ctypes.c_double()
+        self._check(self._lib.fish_timing_read(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
 
     def diagnostics(self):
         out = np.zeros(10)

@@ -48,6 +48,11 @@ struct fish_ctx {
   bool have_state = false;
   std::string err;
   size_t device_bytes = 0;
+  // measurement hook: event pairs around launches of the selected classes
+  int timing_mask = 0;
+  int timing_max = 0;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  int ev_used = 0;
 };
 
 namespace {
@@ -126,6 +131,21 @@ Scalars* scal(fish_ctx* c) { return static_cast<Scalars*>(c->scal.ptr); }
 
 unsigned grid_for(long long threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
 
+// Bracket one kernel launch with events when its class is being timed.
+struct TimedLaunch {
+  fish_ctx* c;
+  int idx = -1;
+  TimedLaunch(fish_ctx* ctx, int cls) : c(ctx) {
+    if ((c->timing_mask & cls) && c->ev_used < c->timing_max) {
+      idx = c->ev_used++;
+      (void)hipEventRecord(c->ev_start[idx], c->stream);
+    }
+  }
+  ~TimedLaunch() {
+    if (idx >= 0) (void)hipEventRecord(c->ev_stop[idx], c->stream);
+  }
+};
+
 int launch_check(fish_ctx* c) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(c, FISH_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -152,6 +172,7 @@ void launch_fluid(fish_ctx* c) {
   constexpr int A = (D == 0) ? 1 : 0;
   constexpr int O = 3 - D - A;
   const long long threads = (long long)c->n[A] * c->n[O] * a.nseg;
+  TimedLaunch tl(c, FISH_KERNEL_FLUID);
   hipLaunchKernelGGL((fish::fluid_sweep_kernel<T, D, GRAV, HSE>), dim3(grid_for(threads)), dim3(kBlock), 0,
                      c->stream, a);
   for (int k = 0; k < 5; ++k) c->cur[k] = 1 - c->cur[k];
@@ -193,7 +214,11 @@ int field_sweep(fish_ctx* c) {
     const long long rA = c->n[A] + ((A == t && c->p.bc[A] == FISH_OUTFLOW) ? 1 : 0);
     const long long rO = c->n[O] + ((O == t && c->p.bc[O] == FISH_OUTFLOW) ? 1 : 0);
     const long long threads = rA * rO * nseg;
-    hipLaunchKernelGGL((fish::field_advect_kernel<T, D>), dim3(grid_for(threads)), dim3(kBlock), 0, c->stream, a);
+    {
+      TimedLaunch tl(c, FISH_KERNEL_ADVECT);
+      hipLaunchKernelGGL((fish::field_advect_kernel<T, D>), dim3(grid_for(threads)), dim3(kBlock), 0, c->stream,
+                         a);
+    }
     int rc = launch_check(c);
     if (rc) return rc;
   }
@@ -206,7 +231,10 @@ int field_sweep(fish_ctx* c) {
   k.sc = scal(c);
   long long nf = 1;
   for (int a2 = 0; a2 < 3; ++a2) nf *= c->n[a2] + ((a2 == D && c->p.bc[a2] == FISH_OUTFLOW) ? 1 : 0);
-  hipLaunchKernelGGL((fish::field_constraint_kernel<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, c->stream, k);
+  {
+    TimedLaunch tl(c, FISH_KERNEL_CONSTRAINT);
+    hipLaunchKernelGGL((fish::field_constraint_kernel<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, c->stream, k);
+  }
   for (int f = 5; f < 8; ++f) c->cur[f] = 1 - c->cur[f];
   return launch_check(c);
 }
@@ -242,7 +270,10 @@ int launch_check_cfl(fish_ctx* c) {
   const long long ncell = (long long)c->n[0] * c->n[1] * c->n[2];
   const unsigned grid = (unsigned)std::min<long long>(grid_for(ncell), 4096);
   hipLaunchKernelGGL(fish::reset_cmax_kernel, dim3(1), dim3(1), 0, c->stream, scal(c));
-  hipLaunchKernelGGL((fish::check_cfl_kernel<T>), dim3(grid), dim3(kBlock), 0, c->stream, a);
+  {
+    TimedLaunch tl(c, FISH_KERNEL_CHECK);
+    hipLaunchKernelGGL((fish::check_cfl_kernel<T>), dim3(grid), dim3(kBlock), 0, c->stream, a);
+  }
   return launch_check(c);
 }
 
@@ -452,6 +483,8 @@ void fish_destroy(fish_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->p.device);
   (void)hipStreamSynchronize(c->stream);
+  for (auto e : c->ev_start) (void)hipEventDestroy(e);
+  for (auto e : c->ev_stop) (void)hipEventDestroy(e);
   for (int b = 0; b < 2; ++b)
     for (int f = 0; f < 8; ++f) dev_free(c, c->fields[b][f]);
   dev_free(c, c->phi);
@@ -567,6 +600,47 @@ int fish_diagnostics(fish_ctx* c, double* out10) {
   if (rc) return rc;
   HIP_TRY(c, hipMemcpyAsync(out10, c->diag_out.ptr, 10 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return FISH_OK;
+}
+
+int fish_timing_enable(fish_ctx* c, int mask, int max_launches) {
+  if (!c) return FISH_ERR_ARG;
+  if (mask < 0 || max_launches < 0 || max_launches > (1 << 20)) return fail(c, FISH_ERR_ARG, "bad timing arguments");
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->timing_mask = 0;
+  c->ev_used = 0;
+  while ((int)c->ev_start.size() < max_launches) {
+    hipEvent_t a, b;
+    HIP_TRY(c, hipEventCreate(&a));
+    hipError_t e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return fail(c, FISH_ERR_DEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    }
+    c->ev_start.push_back(a);
+    c->ev_stop.push_back(b);
+  }
+  c->timing_max = max_launches;
+  c->timing_mask = mask;
+  return FISH_OK;
+}
+
+int fish_timing_read(fish_ctx* c, int* launches, double* total_ms) {
+  if (!c || !launches || !total_ms) return c ? fail(c, FISH_ERR_ARG, "null output") : FISH_ERR_ARG;
+  int rc = set_device(c);
+  if (rc) return rc;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  double sum = 0.0;
+  for (int i = 0; i < c->ev_used; ++i) {
+    float ms = 0.0f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_start[i], c->ev_stop[i]));
+    sum += ms;
+  }
+  *launches = c->ev_used;
+  *total_ms = sum;
+  c->ev_used = 0;
   return FISH_OK;
 }
 
