@@ -147,6 +147,13 @@ enum {
 int fish_timing_enable(fish_ctx* ctx, int mask, int max_launches);
 int fish_timing_read(fish_ctx* ctx, int* launches, double* total_ms);
 
+/* Self-test of the wavefront lane-shift primitive the x sweeps stream with
+ * (no context): one wave of 64 lanes runs two iterations with lane values
+ * v = 100*it + lane; out128[64*it + lane] receives the value one stream
+ * position back (lane-1 of the same iteration, lane 63 of the previous one
+ * for lane 0; -1 before the first).  Synchronous; the caller owns out128. */
+int fish_selftest_lane_shift(int device, float* out128);
+
 #ifdef __cplusplus
 }
 #endif

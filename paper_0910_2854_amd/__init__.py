@@ -54,7 +54,7 @@ class FishError(RuntimeError):
 
 EXPORTS = ("fish_create", "fish_destroy", "fish_last_error", "fish_set_state", "fish_get_state",
            "fish_cfl_dt", "fish_strang_step", "fish_sweep", "fish_diagnostics", "fish_device_bytes",
-           "fish_timing_enable", "fish_timing_read")
+           "fish_timing_enable", "fish_timing_read", "fish_selftest_lane_shift")
 KERNEL_FLUID, KERNEL_ADVECT, KERNEL_CONSTRAINT, KERNEL_CHECK = 1, 2, 4, 8
 
 _lib = None
@@ -84,11 +84,23 @@ def load_library(path: str = LIB_PATH):
     lib.fish_device_bytes.restype = ctypes.c_size_t
     lib.fish_timing_enable.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.fish_timing_read.argtypes = [vp, P(ctypes.c_int), P(d)]
+    lib.fish_selftest_lane_shift.argtypes = [ctypes.c_int, P(ctypes.c_float)]
+    lib.fish_selftest_lane_shift.restype = ctypes.c_int
     for name in ("fish_create", "fish_set_state", "fish_get_state", "fish_cfl_dt", "fish_strang_step",
                  "fish_sweep", "fish_diagnostics", "fish_timing_enable", "fish_timing_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def selftest_lane_shift(device=0):
+    """Run the lane-shift self-test kernel; returns the 128 output values."""
+    lib = load_library()
+    out = np.zeros(128, dtype=np.float32)
+    rc = lib.fish_selftest_lane_shift(int(device), out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    if rc != FISH_OK:
+        raise FishError(rc, "lane-shift self-test failed to run")
+    return out
 
 
 def _dptr(a):

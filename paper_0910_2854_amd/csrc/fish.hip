@@ -153,7 +153,11 @@ int launch_check(fish_ctx* c) {
 }
 
 // ------------------------------------------------------------ sub-operators
-template <typename T, int D, bool GRAV, bool HSE>
+// Whole rows per wave for the x sweeps (lanes policy): about 12 iterations of
+// 64 positions per wave.
+int rows_per_wave(int nx, int halo) { return std::max(1, 768 / (nx + 2 * halo)); }
+
+template <typename T, int D, bool GRAV, bool HSE, int LIM>
 void launch_fluid(fish_ctx* c) {
   fish::FluidArgs<T> a;
   for (int k = 0; k < 5; ++k) {
@@ -165,34 +169,46 @@ void launch_fluid(fish_ctx* c) {
   a.g = make_geo(c);
   a.gamma = c->p.gamma;
   a.alpha = c->p.predictor_alpha;
-  a.limiter = c->p.limiter;
   a.seg = c->seg[D];
   a.nseg = (c->n[D] + a.seg - 1) / a.seg;
+  a.rows_per_wave = rows_per_wave(c->n[0], 3);
   a.sc = scal(c);
-  constexpr int A = (D == 0) ? 1 : 0;
-  constexpr int O = 3 - D - A;
-  const long long threads = (long long)c->n[A] * c->n[O] * a.nseg;
   TimedLaunch tl(c, FISH_KERNEL_FLUID);
-  hipLaunchKernelGGL((fish::fluid_sweep_kernel<T, D, GRAV, HSE>), dim3(grid_for(threads)), dim3(kBlock), 0,
-                     c->stream, a);
-  for (int k = 0; k < 5; ++k) c->cur[k] = 1 - c->cur[k];
+  if (D == 0) {
+    const long long nrows = (long long)c->n[1] * c->n[2];
+    const long long waves = (nrows + a.rows_per_wave - 1) / a.rows_per_wave;
+    hipLaunchKernelGGL((fish::fluid_lanes_kernel<T, GRAV, HSE, LIM>), dim3(grid_for(waves * 64)), dim3(kBlock), 0,
+                       c->stream, a);
+  } else {
+    constexpr int DD = D == 0 ? 1 : D;
+    const long long threads = (long long)c->n[0] * c->n[3 - DD] * a.nseg;
+    hipLaunchKernelGGL((fish::fluid_strided_kernel<T, DD, GRAV, HSE, LIM>), dim3(grid_for(threads)), dim3(kBlock),
+                       0, c->stream, a);
+  }
+}
+
+template <typename T, int D, int LIM>
+void fluid_dispatch_lim(fish_ctx* c) {
+  if (!c->p.gravity)
+    launch_fluid<T, D, false, false, LIM>(c);
+  else if (!c->p.hse)
+    launch_fluid<T, D, true, false, LIM>(c);
+  else
+    launch_fluid<T, D, true, true, LIM>(c);
 }
 
 template <typename T, int D>
 int fluid_dispatch(fish_ctx* c) {
-  if (!c->p.gravity)
-    launch_fluid<T, D, false, false>(c);
-  else if (!c->p.hse)
-    launch_fluid<T, D, true, false>(c);
+  if (c->p.limiter == FISH_MINMOD)
+    fluid_dispatch_lim<T, D, 0>(c);
   else
-    launch_fluid<T, D, true, true>(c);
+    fluid_dispatch_lim<T, D, 1>(c);
+  for (int k = 0; k < 5; ++k) c->cur[k] = 1 - c->cur[k];
   return launch_check(c);
 }
 
-template <typename T, int D>
-int field_sweep(fish_ctx* c) {
-  constexpr int A = (D == 0) ? 1 : 0;
-  constexpr int O = 3 - D - A;
+template <typename T, int D, int LIM>
+int field_sweep_lim(fish_ctx* c) {
   const int tt[2] = {(D + 1) % 3, (D + 2) % 3};
   const Geo g = make_geo(c);
   const int seg = c->seg[D];
@@ -207,17 +223,26 @@ int field_sweep(fish_ctx* c) {
     a.emf = static_cast<T*>(c->emf[s].ptr);
     a.g = g;
     a.t = t;
-    a.limiter = c->p.limiter;
     a.seg = seg;
     a.nseg = nseg;
+    a.rows_per_wave = rows_per_wave(c->n[0], 4);
     a.sc = scal(c);
-    const long long rA = c->n[A] + ((A == t && c->p.bc[A] == FISH_OUTFLOW) ? 1 : 0);
-    const long long rO = c->n[O] + ((O == t && c->p.bc[O] == FISH_OUTFLOW) ? 1 : 0);
-    const long long threads = rA * rO * nseg;
     {
       TimedLaunch tl(c, FISH_KERNEL_ADVECT);
-      hipLaunchKernelGGL((fish::field_advect_kernel<T, D>), dim3(grid_for(threads)), dim3(kBlock), 0, c->stream,
-                         a);
+      if (D == 0) {
+        const long long ry = c->n[1] + ((t == 1 && c->p.bc[1] == FISH_OUTFLOW) ? 1 : 0);
+        const long long rz = c->n[2] + ((t == 2 && c->p.bc[2] == FISH_OUTFLOW) ? 1 : 0);
+        const long long waves = (ry * rz + a.rows_per_wave - 1) / a.rows_per_wave;
+        hipLaunchKernelGGL((fish::advect_lanes_kernel<T, LIM>), dim3(grid_for(waves * 64)), dim3(kBlock), 0,
+                           c->stream, a);
+      } else {
+        constexpr int DD = D == 0 ? 1 : D;
+        constexpr int O = 3 - DD;
+        const long long rA = c->n[0] + ((t == 0 && c->p.bc[0] == FISH_OUTFLOW) ? 1 : 0);
+        const long long rO = c->n[O] + ((O == t && c->p.bc[O] == FISH_OUTFLOW) ? 1 : 0);
+        hipLaunchKernelGGL((fish::advect_strided_kernel<T, DD, LIM>), dim3(grid_for(rA * rO * nseg)), dim3(kBlock),
+                           0, c->stream, a);
+      }
     }
     int rc = launch_check(c);
     if (rc) return rc;
@@ -237,6 +262,11 @@ int field_sweep(fish_ctx* c) {
   }
   for (int f = 5; f < 8; ++f) c->cur[f] = 1 - c->cur[f];
   return launch_check(c);
+}
+
+template <typename T, int D>
+int field_sweep(fish_ctx* c) {
+  return c->p.limiter == FISH_MINMOD ? field_sweep_lim<T, D, 0>(c) : field_sweep_lim<T, D, 1>(c);
 }
 
 template <typename T>
@@ -642,6 +672,18 @@ int fish_timing_read(fish_ctx* c, int* launches, double* total_ms) {
   *total_ms = sum;
   c->ev_used = 0;
   return FISH_OK;
+}
+
+int fish_selftest_lane_shift(int device, float* out128) {
+  if (!out128) return FISH_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return FISH_ERR_DEVICE;
+  float* d = nullptr;
+  if (hipMalloc(&d, 128 * sizeof(float)) != hipSuccess) return FISH_ERR_NOMEM;
+  hipLaunchKernelGGL(fish::lane_shift_selftest_kernel, dim3(1), dim3(64), 0, nullptr, d);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpy(out128, d, 128 * sizeof(float), hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  return e == hipSuccess ? FISH_OK : FISH_ERR_DEVICE;
 }
 
 }  // extern "C"

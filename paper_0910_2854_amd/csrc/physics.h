@@ -3,6 +3,10 @@
 // (double, or float with FP64 pressure recovery) and on the sweep axis D so
 // that every component index is a compile-time constant (no scratch).
 //
+// FP32 arithmetic uses the hardware reciprocal and square root (1 ulp) in
+// place of the IEEE division/square-root sequences; FP64 arithmetic uses one
+// IEEE reciprocal of the density per cell and multiplies.
+//
 // Sect. 2.1-2.4 of the FISH paper; equation numbers are the printed ones.
 #pragma once
 
@@ -13,10 +17,24 @@ namespace fish {
 
 enum { RHO = 0, MX = 1, MY = 2, MZ = 3, EN = 4 };
 
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+
+// 1/rho in FP64 for the pressure recovery: exact division in FP64 mode; in
+// FP32 mode the hardware reciprocal refined by one Newton step in FP64
+// (relative error ~1e-14, far below the FP32 storage rounding of E).
+__device__ __forceinline__ double rinv64(double rho, double) { return 1.0 / rho; }
+__device__ __forceinline__ double rinv64(double rho, float rho32) {
+  const double r0 = (double)__builtin_amdgcn_rcpf(rho32);
+  return r0 * (2.0 - rho * r0);
+}
+
 // Quantities of one cell for a sweep along D (Sect. 2.2).  F is the flux of
 // Eq. (17) with x replaced by D, d the freezing speed |v_D| + c_F of Eq. (21).
 // cS and xiE (= -(E + p), the energy entry of Eq. 50) only for HSE.
-template <typename T>
+template <typename T, bool HSE>
 struct CellQ {
   T u[5];
   T F[5];
@@ -24,36 +42,35 @@ struct CellQ {
   T cS, xiE;
 };
 
-// Pressure from total energy, E = rho e + m^2/(2 rho) + b^2/2, p = (gamma-1) rho e
-// (Sect. 2.1, Eq. 5).  The cancellation step: always evaluated in FP64.
-__device__ __forceinline__ double pressure_fp64(double rho, double mx, double my, double mz, double E,
-                                                double bx, double by, double bz, double gamma,
-                                                double* b2_out) {
+// E = rho e + m^2/(2 rho) + b^2/2 and p = (gamma-1) rho e (Sect. 2.1, Eq. 5):
+// the cancellation step, always evaluated in FP64.
+template <typename T>
+__device__ __forceinline__ T pressure(const T* u, const T* b, double gm1, T* b2_out) {
+  const double rho = (double)u[RHO];
+  const double mx = (double)u[MX], my = (double)u[MY], mz = (double)u[MZ];
+  const double bx = (double)b[0], by = (double)b[1], bz = (double)b[2];
   const double b2 = bx * bx + by * by + bz * bz;
   const double m2 = mx * mx + my * my + mz * mz;
-  *b2_out = b2;
-  return (gamma - 1.0) * (E - 0.5 * m2 / rho - 0.5 * b2);
+  const double ri = rinv64(rho, u[RHO]);
+  *b2_out = (T)b2;
+  return (T)(gm1 * ((double)u[EN] - 0.5 * m2 * ri - 0.5 * b2));
 }
 
 template <typename T, int D, bool HSE>
-__device__ __forceinline__ void cell_quantities(const T* u, const T* b, double gamma, CellQ<T>& c) {
+__device__ __forceinline__ void cell_quantities(const T* u, const T* b, double gamma, CellQ<T, HSE>& c) {
 #pragma unroll
   for (int k = 0; k < 5; ++k) c.u[k] = u[k];
-  const T rho = u[RHO];
-  const T v0 = u[MX] / rho, v1 = u[MY] / rho, v2 = u[MZ] / rho;
-  const T v[3] = {v0, v1, v2};
-  double b2d;
-  const double pd = pressure_fp64((double)rho, (double)u[MX], (double)u[MY], (double)u[MZ], (double)u[EN],
-                                  (double)b[0], (double)b[1], (double)b[2], gamma, &b2d);
-  const T p = (T)pd;
-  const T b2 = (T)b2d;
+  const T ri = rcp(u[RHO]);
+  const T v[3] = {u[MX] * ri, u[MY] * ri, u[MZ] * ri};
+  T b2;
+  const T p = pressure<T>(u, b, gamma - 1.0, &b2);
   const T ptot = p + T(0.5) * b2;
-  const T bv = b[0] * v0 + b[1] * v1 + b[2] * v2;
+  const T bv = b[0] * v[0] + b[1] * v[1] + b[2] * v[2];
   // Directional fast magnetosonic speed (named after Eq. 21).
-  const T a2 = (T)gamma * p / rho;
-  const T q = a2 + b2 / rho;
-  const T disc = q * q - T(4) * a2 * b[D] * b[D] / rho;
-  const T cf = sqrt(T(0.5) * (q + sqrt(disc < T(0) ? T(0) : disc)));
+  const T a2 = (T)gamma * p * ri;
+  const T q = a2 + b2 * ri;
+  const T disc = q * q - T(4) * a2 * b[D] * b[D] * ri;
+  const T cf = fsqrt(T(0.5) * (q + fsqrt(disc < T(0) ? T(0) : disc)));
   const T md = u[MX + D];
   c.F[RHO] = md;
 #pragma unroll
@@ -67,7 +84,7 @@ __device__ __forceinline__ void cell_quantities(const T* u, const T* b, double g
   c.cF = cf;
   c.d = fabs(v[D]) + cf;
   if (HSE) {
-    c.cS = sqrt(a2);
+    c.cS = fsqrt(a2);
     c.xiE = -(u[EN] + p);
   } else {
     c.cS = T(0);
@@ -84,12 +101,12 @@ __device__ __forceinline__ T minmod(T a, T b) {
 }
 template <typename T>
 __device__ __forceinline__ T vanleer(T a, T b) {
-  if (a * b <= T(0)) return T(0);
-  return T(2) * a * b / (a + b);
+  const T ab = a * b;
+  return ab > T(0) ? T(2) * ab * rcp(a + b) : T(0);
 }
-template <typename T>
-__device__ __forceinline__ T limit(T a, T b, int limiter) {
-  return limiter == 0 ? minmod(a, b) : vanleer(a, b);
+template <typename T, int LIM>
+__device__ __forceinline__ T limit(T a, T b) {
+  return LIM == 0 ? minmod(a, b) : vanleer(a, b);
 }
 
 // Dissipation Q_j at the interface between cells L and R, so that the
@@ -98,7 +115,8 @@ __device__ __forceinline__ T limit(T a, T b, int limiter) {
 //   HSE:    Q = max(|v_L|, |v_R|) du + max(cF_L, cF_R) minmod(du - g, du),
 //           g = (xi_L + xi_R)/2 (phi_R - phi_L)/(cS_L cS_R), Eqs. (50)-(57).
 template <typename T, bool HSE>
-__device__ __forceinline__ void dissipation(const CellQ<T>& L, const CellQ<T>& R, T phiL, T phiR, T* Q) {
+__device__ __forceinline__ void dissipation(const CellQ<T, HSE>& L, const CellQ<T, HSE>& R, T phiL, T phiR,
+                                            T* Q) {
   if (!HSE) {
     const T dmax = L.d > R.d ? L.d : R.d;
 #pragma unroll
@@ -107,7 +125,7 @@ __device__ __forceinline__ void dissipation(const CellQ<T>& L, const CellQ<T>& R
     const T avL = fabs(L.vd), avR = fabs(R.vd);
     const T dadv = avL > avR ? avL : avR;
     const T dac = L.cF > R.cF ? L.cF : R.cF;
-    const T scale = (phiR - phiL) / (L.cS * R.cS);
+    const T scale = (phiR - phiL) * rcp(L.cS * R.cS);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       const T du = R.u[k] - L.u[k];
@@ -121,10 +139,10 @@ __device__ __forceinline__ void dissipation(const CellQ<T>& L, const CellQ<T>& R
 }
 
 // Unsplit gravitational source of cell i, Eq. (42) with the sign of Eq. (36):
-// S = -(0, rho e_D, m_D) (phi_i+1 - phi_i-1)/(2 h).
+// S = -(0, rho e_D, m_D) (phi_i+1 - phi_i-1)/(2 h); inv2h = 1/(2 h).
 template <typename T, int D>
-__device__ __forceinline__ void gravity_source(T rho, T mD, T dphi2, T h, T* S) {
-  const T gr = dphi2 / (T(2) * h);
+__device__ __forceinline__ void gravity_source(T rho, T mD, T dphi2, T inv2h, T* S) {
+  const T gr = dphi2 * inv2h;
 #pragma unroll
   for (int k = 0; k < 5; ++k) S[k] = T(0);
   S[MX + D] = -rho * gr;

@@ -7,17 +7,19 @@
 // 0 and is never stored.  Ghost cells are never stored either: every load
 // maps its index (periodic wrap, or clamp for zeroth-order extrapolation).
 //
-// Fluid sweep L_d (Sect. 2.2-2.3): one thread streams one pencil segment
-// along d through a register window -- the predictor of cell c-1 and the
-// corrector of cell c-3 are produced when cell c is loaded, so each cell is
-// read from HBM once per pass plus a 3-cell halo per segment end (the 7-cell
-// stencil of Sect. 3).  Lanes of a wave are adjacent along x for the y and z
-// sweeps, so every load and store is coalesced across the wave.
-//
-// Field sweep B_d (Sect. 2.4): transverse advection of b_t1 and b_t2 along d
-// by the same streaming scheme (4-cell halo: Eq. 66 smooths once more), which
-// writes the edge fluxes (EMFs); then the constraint update of b_d from those
-// EMFs (Eq. 64).
+// Both sweeps are written once as a streaming pipeline over the positions of
+// a pencil: when cell c is loaded, the predictor of cell c-1 and the
+// corrector of cell c-3 are produced (the 7-cell stencil of Sect. 3), so each
+// cell is read from HBM once per pass.  "The value one position back" comes
+// from one of two policies:
+//   Strided (y and z sweeps): a lane owns a pencil segment and walks it; the
+//     previous position is the lane's own register from the last iteration.
+//     Adjacent lanes are adjacent along x, so every access is coalesced.
+//   Lanes (x sweep): the 64 lanes of a wave hold 64 consecutive positions of
+//     a stream of whole x rows (each row padded by its 3-cell halos); the
+//     previous position is the neighbour lane (DPP wave shift), lane 0 taking
+//     lane 63 of the previous iteration.  Again every access is coalesced and
+//     no row is transposed.
 #pragma once
 
 #include "physics.h"
@@ -40,6 +42,79 @@ struct Scalars {
   int pad;
 };
 
+// ------------------------------------------------------------ position history
+// prev(cur, h): the value this quantity had one stream position earlier.
+struct StridedHist {
+  template <typename V>
+  __device__ __forceinline__ static V prev(const V& cur, V& h) {
+    V p = h;
+    h = cur;
+    return p;
+  }
+};
+
+__device__ __forceinline__ int lane_prev_bits(int cur, int& carry) {
+  // wave_shr:1 -- lane i takes lane i-1; lane 0 keeps `old` = carry (whose
+  // lane 0 holds lane 63 of the previous iteration); then carry = wave_ror:1.
+  const int o = __builtin_amdgcn_update_dpp(carry, cur, 0x138, 0xf, 0xf, false);
+  carry = __builtin_amdgcn_mov_dpp(cur, 0x13C, 0xf, 0xf, false);
+  return o;
+}
+__device__ __forceinline__ float lane_prev(float cur, float& carry) {
+  int c = __float_as_int(carry);
+  const int o = lane_prev_bits(__float_as_int(cur), c);
+  carry = __int_as_float(c);
+  return __int_as_float(o);
+}
+__device__ __forceinline__ double lane_prev(double cur, double& carry) {
+  const long long cb = __double_as_longlong(cur);
+  long long kb = __double_as_longlong(carry);
+  int klo = (int)(kb & 0xffffffffll), khi = (int)(kb >> 32);
+  const int olo = lane_prev_bits((int)(cb & 0xffffffffll), klo);
+  const int ohi = lane_prev_bits((int)(cb >> 32), khi);
+  carry = __longlong_as_double(((long long)khi << 32) | (unsigned int)klo);
+  return __longlong_as_double(((long long)ohi << 32) | (unsigned int)olo);
+}
+
+struct LaneHist {
+  template <typename T>
+  __device__ __forceinline__ static T prev(const T& cur, T& h) {
+    return lane_prev(cur, h);
+  }
+  template <typename T, bool HSE>
+  __device__ __forceinline__ static CellQ<T, HSE> prev(const CellQ<T, HSE>& cur, CellQ<T, HSE>& h) {
+    CellQ<T, HSE> o;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      o.u[k] = lane_prev(cur.u[k], h.u[k]);
+      o.F[k] = lane_prev(cur.F[k], h.F[k]);
+    }
+    o.d = lane_prev(cur.d, h.d);
+    if (HSE) {
+      o.vd = lane_prev(cur.vd, h.vd);
+      o.cF = lane_prev(cur.cF, h.cF);
+      o.cS = lane_prev(cur.cS, h.cS);
+      o.xiE = lane_prev(cur.xiE, h.xiE);
+    } else {
+      o.vd = o.cF = o.cS = o.xiE = T(0);
+    }
+    return o;
+  }
+};
+
+template <typename T, int N>
+struct Vec {
+  T v[N];
+};
+template <typename H, typename T, int N>
+__device__ __forceinline__ Vec<T, N> prev_vec(const Vec<T, N>& cur, Vec<T, N>& h) {
+  Vec<T, N> o;
+#pragma unroll
+  for (int k = 0; k < N; ++k) o.v[k] = H::prev(cur.v[k], h.v[k]);
+  return o;
+}
+
+// ------------------------------------------------------------ L_d pipeline
 template <typename T>
 struct FluidArgs {
   const T* u[5];
@@ -48,8 +123,8 @@ struct FluidArgs {
   const T* phi;
   Geo g;
   double gamma, alpha;
-  int limiter;
-  int seg, nseg;
+  int seg, nseg;   // strided: segment length along D and segments per pencil
+  int rows_per_wave; // lanes: whole rows per wave
   const Scalars* sc;
 };
 
@@ -66,11 +141,145 @@ __device__ __forceinline__ T load_phi(const T* phi, long long base, long long st
   return p0 + (T)(s - (n - 1)) * (p0 - p1);
 }
 
-// ------------------------------------------------------------ L_d
-template <typename T, int D, bool GRAV, bool HSE>
-__global__ __launch_bounds__(256) void fluid_sweep_kernel(FluidArgs<T> a) {
-  constexpr int A = (D == 0) ? 1 : 0;  // axis adjacent lanes walk along
-  constexpr int O = 3 - D - A;
+template <typename T>
+struct FluidConsts {
+  T k_half, k_full, half_dt, dt, inv2h, halfalpha;
+  double gamma;
+};
+
+template <typename T, bool HSE>
+struct FluidHist {
+  CellQ<T, HSE> q0, q1;
+  Vec<T, 3> bc;
+  Vec<T, 5> F1, ap, am, Lp, bs, F2, ua, ub;
+  T ph1, ph2, ph3, ph4, rp1, rp2, mp1, mp2;
+  __device__ void zero() {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      q0.u[k] = q0.F[k] = q1.u[k] = q1.F[k] = T(0);
+      F1.v[k] = ap.v[k] = am.v[k] = Lp.v[k] = bs.v[k] = F2.v[k] = ua.v[k] = ub.v[k] = T(0);
+    }
+    q0.vd = q0.cF = q0.d = q0.cS = q0.xiE = T(0);
+    q1.vd = q1.cF = q1.d = q1.cS = q1.xiE = T(0);
+    bc.v[0] = bc.v[1] = bc.v[2] = T(0);
+    ph1 = ph2 = ph3 = ph4 = rp1 = rp2 = mp1 = mp2 = T(0);
+  }
+};
+
+// One stream position: loads of cell c in (uc, bc, phc); returns the
+// corrected state of cell c-3 in un.  u3 is the state of cell c-3 when the
+// caller reloads it (lanes policy); otherwise the history chain supplies it.
+template <typename T, int D, bool GRAV, bool HSE, int LIM, typename H, bool RELOAD_U3>
+__device__ __forceinline__ void fluid_position(const T* uc, const Vec<T, 3>& bcc, T phc, const T* u3_loaded,
+                                               const FluidConsts<T>& k, FluidHist<T, HSE>& h, T* un) {
+  // cell quantities of u at c and c-1
+  CellQ<T, HSE> q0;
+  cell_quantities<T, D, HSE>(uc, bcc.v, k.gamma, q0);
+  const CellQ<T, HSE> q0m = H::prev(q0, h.q0);
+  const Vec<T, 3> bcm = prev_vec<H>(bcc, h.bc);
+  T phm1 = T(0), phm2 = T(0), phm3 = T(0), phm4 = T(0);
+  if (GRAV || HSE) {
+    phm1 = H::prev(phc, h.ph1);
+    phm2 = H::prev(phm1, h.ph2);
+    phm3 = H::prev(phm2, h.ph3);
+    phm4 = H::prev(phm3, h.ph4);
+  }
+  // predictor flux at interface c-1/2 (Eq. 24, dissipation scaled by alpha)
+  T Q[5];
+  Vec<T, 5> F1;
+  dissipation<T, HSE>(q0m, q0, phm1, phc, Q);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) F1.v[i] = T(0.5) * (q0m.F[i] + q0.F[i]) - k.halfalpha * Q[i];
+  const Vec<T, 5> F1m = prev_vec<H>(F1, h.F1);
+  // predictor half step of cell c-1 (Eq. 41)
+  T up[5];
+  if (GRAV) {
+    T S[5];
+    gravity_source<T, D>(q0m.u[RHO], q0m.u[MX + D], phc - phm2, k.inv2h, S);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) up[i] = q0m.u[i] - k.k_half * (F1.v[i] - F1m.v[i]) + k.half_dt * S[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) up[i] = q0m.u[i] - k.k_half * (F1.v[i] - F1m.v[i]);
+  }
+  // cell quantities of the half-step state of c-1 (field unchanged), and of c-2
+  CellQ<T, HSE> q1;
+  cell_quantities<T, D, HSE>(up, bcm.v, k.gamma, q1);
+  const CellQ<T, HSE> q1m = H::prev(q1, h.q1);
+  // relaxed flux differences across interface c-3/2 (between c-2 and c-1)
+  T Qc[5];
+  Vec<T, 5> ap, am, bs;
+  dissipation<T, HSE>(q1m, q1, phm2, phm1, Qc);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const T dF = q1.F[i] - q1m.F[i];
+    ap.v[i] = T(0.5) * (dF + Qc[i]);
+    am.v[i] = T(0.5) * (dF - Qc[i]);
+    bs.v[i] = T(0.5) * (q1m.F[i] + q1.F[i]) - T(0.5) * Qc[i];
+  }
+  const Vec<T, 5> apm = prev_vec<H>(ap, h.ap);
+  const Vec<T, 5> amm = prev_vec<H>(am, h.am);
+  const Vec<T, 5> bsm = prev_vec<H>(bs, h.bs);
+  // limited second-order flux at interface c-5/2 (Eq. 34)
+  Vec<T, 5> Lp, F2;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) Lp.v[i] = limit<T, LIM>(apm.v[i], ap.v[i]);
+  const Vec<T, 5> Lpm = prev_vec<H>(Lp, h.Lp);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) F2.v[i] = bsm.v[i] + T(0.5) * (Lpm.v[i] - limit<T, LIM>(amm.v[i], am.v[i]));
+  const Vec<T, 5> F2m = prev_vec<H>(F2, h.F2);
+  // state of cell c-3 before the sweep
+  T u3[5];
+  if (RELOAD_U3) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) u3[i] = u3_loaded[i];
+  } else {
+    Vec<T, 5> um1;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) um1.v[i] = q0m.u[i];
+    const Vec<T, 5> um2 = prev_vec<H>(um1, h.ua);
+    const Vec<T, 5> um3 = prev_vec<H>(um2, h.ub);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) u3[i] = um3.v[i];
+  }
+  // corrector of cell c-3 (Eq. 43)
+  if (GRAV) {
+    const T rpm2 = H::prev(up[RHO], h.rp1);   // rho' of c-2
+    const T rpm3 = H::prev(rpm2, h.rp2);      // rho' of c-3
+    const T mpm2 = H::prev(up[MX + D], h.mp1);
+    const T mpm3 = H::prev(mpm2, h.mp2);
+    T S[5];
+    gravity_source<T, D>(rpm3, mpm3, phm2 - phm4, k.inv2h, S);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) un[i] = u3[i] - k.k_full * (F2.v[i] - F2m.v[i]) + k.dt * S[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) un[i] = u3[i] - k.k_full * (F2.v[i] - F2m.v[i]);
+  }
+  (void)phm3;
+}
+
+template <typename T>
+__device__ __forceinline__ FluidConsts<T> fluid_consts(const FluidArgs<T>& a, int D) {
+  const double dt = a.sc->dt;
+  const double h = a.g.h[D];
+  FluidConsts<T> k;
+  k.k_half = (T)(dt / (2.0 * h));
+  k.k_full = (T)(dt / h);
+  k.half_dt = (T)(0.5 * dt);
+  k.dt = (T)dt;
+  k.inv2h = (T)(1.0 / (2.0 * h));
+  k.halfalpha = (T)(0.5 * a.alpha);
+  k.gamma = a.gamma;
+  return k;
+}
+
+// Strided policy (D = y or z): one thread per pencil segment.
+template <typename T, int D, bool GRAV, bool HSE, int LIM>
+__global__ __launch_bounds__(256) void fluid_strided_kernel(FluidArgs<T> a) {
+  static_assert(D != 0, "x sweeps use the lanes policy");
+  constexpr int A = 0;  // lanes walk along x
+  constexpr int O = 3 - D;
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   const Geo& g = a.g;
   const int nA = g.n[A], nO = g.n[O], nD = g.n[D];
@@ -83,139 +292,93 @@ __global__ __launch_bounds__(256) void fluid_sweep_kernel(FluidArgs<T> a) {
   const int sg = (int)(r / nO);
   const int s0 = sg * a.seg;
   const int s1 = min(nD, s0 + a.seg);
-
   int c[3];
   c[A] = ia;
   c[O] = io;
   c[D] = 0;
   const long long stD = g.st[D];
   const long long base = (long long)c[A] * g.st[A] + (long long)c[O] * g.st[O];
-  // high transverse faces of the cell (Eq. 9-11 layout: face f+1 closes cell f)
   const long long hi1 = base + (long long)(map_face(c[T1] + 1, g.n[T1], g.bc[T1]) - c[T1]) * g.st[T1];
   const long long hi2 = base + (long long)(map_face(c[T2] + 1, g.n[T2], g.bc[T2]) - c[T2]) * g.st[T2];
-
-  const double dt = a.sc->dt;
-  const T k_half = (T)(dt / (2.0 * g.h[D]));
-  const T k_full = (T)(dt / g.h[D]);
-  const T half_dt = (T)(0.5 * dt);
-  const T dtT = (T)dt;
-  const T h = (T)g.h[D];
-  const T alpha = (T)a.alpha;
-  const T halfalpha = T(0.5) * alpha;
-  const double gamma = a.gamma;
-  const int lim = a.limiter;
-
-  CellQ<T> q0p, q1p;
-  T u2[5], u3[5], bcp[3], F1p[5], app[5], amp[5], basep[5], Lpp[5], F2p[5];
-  T ph1 = T(0), ph2 = T(0), ph3 = T(0), ph4 = T(0);
-  T rp2 = T(0), mp2 = T(0), rp3 = T(0), mp3 = T(0);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    q0p.u[k] = q0p.F[k] = q1p.u[k] = q1p.F[k] = T(0);
-    u2[k] = u3[k] = F1p[k] = app[k] = amp[k] = basep[k] = Lpp[k] = F2p[k] = T(0);
-  }
-  q0p.vd = q0p.cF = q0p.d = q0p.cS = q0p.xiE = T(0);
-  q1p.vd = q1p.cF = q1p.d = q1p.cS = q1p.xiE = T(0);
-  bcp[0] = bcp[1] = bcp[2] = T(0);
-
+  const FluidConsts<T> k = fluid_consts(a, D);
+  FluidHist<T, HSE> h;
+  h.zero();
   const int npos = (s1 - s0) + 6;
+#pragma unroll 2
   for (int it = 0; it < npos; ++it) {
-    const int s = s0 - 3 + it;  // cell c loaded at this position
-    const int ms = map_cell(s, nD, g.bc[D]);
-    const long long off = (long long)ms * stD;
-    T uc[5], bc[3];
+    const int s = s0 - 3 + it;
+    const long long off = (long long)map_cell(s, nD, g.bc[D]) * stD;
+    T uc[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) uc[k] = a.u[k][base + off];
-    {
-      const long long f0 = (long long)map_face(s, nD, g.bc[D]) * stD;
-      const long long f1 = (long long)map_face(s + 1, nD, g.bc[D]) * stD;
-      bc[D] = T(0.5) * (a.b[D][base + f0] + a.b[D][base + f1]);
-      bc[T1] = T(0.5) * (a.b[T1][base + off] + a.b[T1][hi1 + off]);
-      bc[T2] = T(0.5) * (a.b[T2][base + off] + a.b[T2][hi2 + off]);
-    }
+    for (int i = 0; i < 5; ++i) uc[i] = a.u[i][base + off];
+    Vec<T, 3> bcc;
+    const long long f0 = (long long)map_face(s, nD, g.bc[D]) * stD;
+    const long long f1 = (long long)map_face(s + 1, nD, g.bc[D]) * stD;
+    bcc.v[D] = T(0.5) * (a.b[D][base + f0] + a.b[D][base + f1]);
+    bcc.v[T1] = T(0.5) * (a.b[T1][base + off] + a.b[T1][hi1 + off]);
+    bcc.v[T2] = T(0.5) * (a.b[T2][base + off] + a.b[T2][hi2 + off]);
     T phc = T(0);
     if (GRAV) phc = load_phi(a.phi, base, stD, s, nD, g.bc[D]);
-
-    // cell quantities of u at c
-    CellQ<T> q0;
-    cell_quantities<T, D, HSE>(uc, bc, gamma, q0);
-    // predictor flux at the interface c-1/2 (Eq. 24, dissipation scaled by alpha)
-    T Q[5], F1[5];
-    dissipation<T, HSE>(q0p, q0, ph1, phc, Q);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) F1[k] = T(0.5) * (q0p.F[k] + q0.F[k]) - halfalpha * Q[k];
-    // predictor half step of cell c-1 (Eq. 41)
-    T up[5];
-    if (GRAV) {
-      T S[5];
-      gravity_source<T, D>(q0p.u[RHO], q0p.u[MX + D], phc - ph2, h, S);
-#pragma unroll
-      for (int k = 0; k < 5; ++k) up[k] = q0p.u[k] - k_half * (F1[k] - F1p[k]) + half_dt * S[k];
-    } else {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) up[k] = q0p.u[k] - k_half * (F1[k] - F1p[k]);
-    }
-    // cell quantities of the half-step state of cell c-1 (field unchanged)
-    CellQ<T> q1;
-    cell_quantities<T, D, HSE>(up, bcp, gamma, q1);
-    // relaxed flux differences across interface c-3/2 (between c-2 and c-1)
-    T Qc[5], ap[5], am[5], bs[5];
-    dissipation<T, HSE>(q1p, q1, ph2, ph1, Qc);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const T dF = q1.F[k] - q1p.F[k];
-      ap[k] = T(0.5) * (dF + Qc[k]);
-      am[k] = T(0.5) * (dF - Qc[k]);
-      bs[k] = T(0.5) * (q1p.F[k] + q1.F[k]) - T(0.5) * Qc[k];
-    }
-    // limited second-order flux at interface c-5/2 (Eq. 34) and the
-    // corrector of cell c-3 (Eq. 43)
-    T Lp[5], F2[5], un[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      Lp[k] = limit(app[k], ap[k], lim);
-      const T Lm = limit(amp[k], am[k], lim);
-      F2[k] = basep[k] + T(0.5) * (Lpp[k] - Lm);
-    }
-    if (GRAV) {
-      T S[5];
-      gravity_source<T, D>(rp3, mp3, ph2 - ph4, h, S);
-#pragma unroll
-      for (int k = 0; k < 5; ++k) un[k] = u3[k] - k_full * (F2[k] - F2p[k]) + dtT * S[k];
-    } else {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) un[k] = u3[k] - k_full * (F2[k] - F2p[k]);
-    }
+    T un[5];
+    fluid_position<T, D, GRAV, HSE, LIM, StridedHist, false>(uc, bcc, phc, nullptr, k, h, un);
     if (it >= 6) {
       const long long o = base + (long long)(s - 3) * stD;
 #pragma unroll
-      for (int k = 0; k < 5; ++k) a.uo[k][o] = un[k];
+      for (int i = 0; i < 5; ++i) a.uo[i][o] = un[i];
     }
-    // shift the window
+  }
+}
+
+// Lanes policy (D = x): each wave streams rows_per_wave whole x rows.
+template <typename T, bool GRAV, bool HSE, int LIM>
+__global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidArgs<T> a) {
+  constexpr int D = 0;
+  const Geo& g = a.g;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int L = nx + 6;                     // stream positions per row
+  const long long nrows = (long long)ny * nz;
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const long long r0 = wave * a.rows_per_wave;
+  if (r0 >= nrows) return;  // whole wave exits together
+  const int rows = (int)min((long long)a.rows_per_wave, nrows - r0);
+  const int npos = rows * L;
+  const int nit = (npos + 63) >> 6;
+  const FluidConsts<T> k = fluid_consts(a, D);
+  FluidHist<T, HSE> h;
+  h.zero();
+  for (int it = 0; it < nit; ++it) {
+    const int q = (it << 6) + lane;
+    const bool valid = q < npos;
+    const int qq = valid ? q : npos - 1;
+    const int rr = qq / L;
+    const int cpos = qq - rr * L - 3;        // cell index along x (-3 .. nx+2)
+    const long long row = r0 + rr;
+    const int y = (int)(row % ny), z = (int)(row / ny);
+    const long long base = (long long)y * g.st[1] + (long long)z * g.st[2];
+    const long long yhi = base + (long long)(map_face(y + 1, ny, g.bc[1]) - y) * g.st[1];
+    const long long zhi = base + (long long)(map_face(z + 1, nz, g.bc[2]) - z) * g.st[2];
+    const int ms = map_cell(cpos, nx, g.bc[0]);
+    T uc[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      F2p[k] = F2[k];
-      Lpp[k] = Lp[k];
-      basep[k] = bs[k];
-      app[k] = ap[k];
-      amp[k] = am[k];
-      F1p[k] = F1[k];
-      u3[k] = u2[k];
-      u2[k] = q0p.u[k];
+    for (int i = 0; i < 5; ++i) uc[i] = a.u[i][base + ms];
+    Vec<T, 3> bcc;
+    bcc.v[0] = T(0.5) * (a.b[0][base + map_face(cpos, nx, g.bc[0])] + a.b[0][base + map_face(cpos + 1, nx, g.bc[0])]);
+    bcc.v[1] = T(0.5) * (a.b[1][base + ms] + a.b[1][yhi + ms]);
+    bcc.v[2] = T(0.5) * (a.b[2][base + ms] + a.b[2][zhi + ms]);
+    T phc = T(0);
+    if (GRAV) phc = load_phi(a.phi, base, 1, cpos, nx, g.bc[0]);
+    const int m3 = map_cell(cpos - 3, nx, g.bc[0]);
+    T u3[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) u3[i] = a.u[i][base + m3];
+    T un[5];
+    fluid_position<T, D, GRAV, HSE, LIM, LaneHist, true>(uc, bcc, phc, u3, k, h, un);
+    const int co = cpos - 3;
+    if (valid && co >= 0 && co < nx) {
+#pragma unroll
+      for (int i = 0; i < 5; ++i) a.uo[i][base + co] = un[i];
     }
-    q1p = q1;
-    q0p = q0;
-    rp3 = rp2;
-    mp3 = mp2;
-    rp2 = up[RHO];
-    mp2 = up[MX + D];
-    bcp[0] = bc[0];
-    bcp[1] = bc[1];
-    bcp[2] = bc[2];
-    ph4 = ph3;
-    ph3 = ph2;
-    ph2 = ph1;
-    ph1 = phc;
   }
 }
 
@@ -229,22 +392,69 @@ struct AdvectArgs {
   T* emf;         // edge flux output, layout of the fields
   Geo g;
   int t;          // transverse axis
-  int limiter;
   int seg, nseg;
+  int rows_per_wave;
   const Scalars* sc;
 };
 
-// One face row of b_t along D: Eq. (65) face velocity, Eq. (66) smoothing,
-// Eq. (68) interface velocity, Eq. (67) first-order upwind predictor flux,
-// second-order limited upwind corrector flux (end of Sect. 2.4), Eq. (63).
-template <typename T, int D>
-__global__ __launch_bounds__(256) void field_advect_kernel(AdvectArgs<T> a) {
-  constexpr int A = (D == 0) ? 1 : 0;
-  constexpr int O = 3 - D - A;
+template <typename T>
+struct AdvectHist {
+  T w1, w2, b1, b2, b3, b4, f2, p1, vb1, vb2, vb3, fp3, fp4, fp5, P2;
+  __device__ void zero() { w1 = w2 = b1 = b2 = b3 = b4 = f2 = p1 = vb1 = vb2 = vb3 = fp3 = fp4 = fp5 = P2 = T(0); }
+};
+
+// One position of one face row of b_t along D: Eq. (65) face velocity w0 at
+// cell c, Eq. (66) smoothing, Eq. (68) interface velocity, Eq. (67)
+// first-order upwind predictor flux, second-order limited upwind corrector
+// flux (end of Sect. 2.4), Eq. (63).  Outputs the new b_t of cell c-4 and
+// the edge flux at d-face c-3 (the interface between c-4 and c-3).
+template <typename T, int LIM, typename H, bool RELOAD_B4>
+__device__ __forceinline__ void advect_position(T w0, T bb, T b4_loaded, T k_half, T k_full, AdvectHist<T>& h,
+                                                T& bn, T& emf) {
+  const T w1 = H::prev(w0, h.w1);
+  const T w2 = H::prev(w1, h.w2);
+  const T vbc = T(0.25) * (w2 + T(2) * w1 + w0);   // v-bar of c-1
+  const T b1 = H::prev(bb, h.b1);                   // b of c-1
+  const T fc = vbc * b1;                            // f of c-1
+  const T vb1 = H::prev(vbc, h.vb1);                // v-bar of c-2
+  const T V = T(0.5) * (vb1 + vbc);                 // interface c-3/2
+  const T f2 = H::prev(fc, h.f2);                   // f of c-2
+  const T P1 = V > T(0) ? f2 : fc;                  // Phi1 at c-3/2
+  const T p1 = H::prev(P1, h.p1);                   // Phi1 at c-5/2
+  const T b2 = H::prev(b1, h.b2);                   // b of c-2
+  const T bp = b2 - k_half * (P1 - p1);             // b' of c-2
+  const T fp2 = vb1 * bp;                           // f' of c-2
+  const T vb2 = H::prev(vb1, h.vb2);                // v-bar of c-3
+  const T vb3 = H::prev(vb2, h.vb3);                // v-bar of c-4
+  const T V7 = T(0.5) * (vb3 + vb2);                // interface c-7/2
+  const T fp3 = H::prev(fp2, h.fp3);
+  const T fp4 = H::prev(fp3, h.fp4);
+  const T fp5 = H::prev(fp4, h.fp5);
+  T P2c;
+  if (V7 > T(0))
+    P2c = fp4 + T(0.5) * limit<T, LIM>(fp4 - fp5, fp3 - fp4);
+  else
+    P2c = fp3 - T(0.5) * limit<T, LIM>(fp3 - fp4, fp2 - fp3);
+  const T P2 = H::prev(P2c, h.P2);                  // Phi2 at c-9/2
+  T b4;
+  if (RELOAD_B4) {
+    b4 = b4_loaded;
+  } else {
+    const T b3 = H::prev(b2, h.b3);
+    b4 = H::prev(b3, h.b4);
+  }
+  bn = b4 - k_full * (P2c - P2);
+  emf = P2c;
+}
+
+template <typename T, int D, int LIM>
+__global__ __launch_bounds__(256) void advect_strided_kernel(AdvectArgs<T> a) {
+  static_assert(D != 0, "x sweeps use the lanes policy");
+  constexpr int A = 0;
+  constexpr int O = 3 - D;
   const Geo& g = a.g;
   const int t = a.t;
   const int nD = g.n[D];
-  // face rows along t include face n_t on an outflow axis
   const int rA = g.n[A] + ((A == t && g.bc[A] == 1) ? 1 : 0);
   const int rO = g.n[O] + ((O == t && g.bc[O] == 1) ? 1 : 0);
   const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -258,78 +468,86 @@ __global__ __launch_bounds__(256) void field_advect_kernel(AdvectArgs<T> a) {
   const int s1 = min(nD, s0 + a.seg);
   const bool last = (s1 == nD);
   const bool outD = g.bc[D] == 1;
-
   int c[3];
   c[A] = ia;
   c[O] = io;
   c[D] = 0;
   const long long stD = g.st[D];
-  const long long base = (long long)c[A] * g.st[A] + (long long)c[O] * g.st[O];  // the face row
-  // the two cells sharing the t-face: t-index ft-1 and ft (mapped)
+  const long long base = (long long)c[A] * g.st[A] + (long long)c[O] * g.st[O];
   const int ft = c[t];
   const long long cell_lo = base + (long long)(map_cell(ft - 1, g.n[t], g.bc[t]) - ft) * g.st[t];
   const long long cell_hi = base + (long long)(map_cell(ft, g.n[t], g.bc[t]) - ft) * g.st[t];
-
   const double dt = a.sc->dt;
   const T k_half = (T)(dt / (2.0 * g.h[D]));
   const T k_full = (T)(dt / g.h[D]);
-  const int lim = a.limiter;
-
-  T w1 = T(0), w2 = T(0);                  // w at c-1, c-2
-  T vb1 = T(0), vb2 = T(0), vb3 = T(0);  // v-bar at c-2, c-3, c-4
-  T b1 = T(0), b2 = T(0), b3 = T(0), b4 = T(0);  // b_t at c-1 .. c-4
-  T f2 = T(0);                              // f at c-2
-  T p1 = T(0);                              // Phi1 at interface c-5/2
-  T fp3 = T(0), fp4 = T(0), fp5 = T(0);     // f' at c-3, c-4, c-5
-  T P2 = T(0);                              // Phi2 at interface c-9/2
-
+  AdvectHist<T> h;
+  h.zero();
   const int npos = (s1 - s0) + 8;
+#pragma unroll 2
   for (int it = 0; it < npos; ++it) {
     const int s = s0 - 4 + it;
     const long long off = (long long)map_cell(s, nD, g.bc[D]) * stD;
-    // Eq. (65): v_d at the t-face, mean of the two cells sharing it
-    const T vlo = a.md[cell_lo + off] / a.rho[cell_lo + off];
-    const T vhi = a.md[cell_hi + off] / a.rho[cell_hi + off];
+    const T vlo = a.md[cell_lo + off] * rcp(a.rho[cell_lo + off]);
+    const T vhi = a.md[cell_hi + off] * rcp(a.rho[cell_hi + off]);
     const T w0 = T(0.5) * (vlo + vhi);
     const T bb = a.bt[base + off];
-    // Eq. (66) at c-1
-    const T vbc = T(0.25) * (w2 + T(2) * w1 + w0);
-    const T fc = vbc * b1;                 // f at c-1
-    // Eq. (68), interface c-3/2 between c-2 and c-1; Eq. (67) upwind flux
-    const T V = T(0.5) * (vb1 + vbc);
-    const T P1 = V > T(0) ? f2 : fc;
-    // half-step predictor of cell c-2 and its flux
-    const T bp = b2 - k_half * (P1 - p1);
-    const T fp2 = vb1 * bp;
-    // corrector flux at interface c-7/2 (between c-4 and c-3), upwind by V there
-    const T V7 = T(0.5) * (vb3 + vb2);
-    T P2c;
-    if (V7 > T(0))
-      P2c = fp4 + T(0.5) * limit(fp4 - fp5, fp3 - fp4, lim);
-    else
-      P2c = fp3 - T(0.5) * limit(fp3 - fp4, fp2 - fp3, lim);
-    // advection update of cell c-4 (Eq. 63 along d)
-    const T bn = b4 - k_full * (P2c - P2);
+    T bn, e;
+    advect_position<T, LIM, StridedHist, false>(w0, bb, T(0), k_half, k_full, h, bn, e);
     if (it >= 8) a.bto[base + (long long)(s - 4) * stD] = bn;
-    // EMF at d-face c-3 (interface c-7/2)
     const int fd = s - 3;
-    if (it >= 7 && (fd < s1 || (last && outD && fd == nD))) a.emf[base + (long long)fd * stD] = P2c;
-    // shift
-    P2 = P2c;
-    fp5 = fp4;
-    fp4 = fp3;
-    fp3 = fp2;
-    p1 = P1;
-    f2 = fc;
-    vb3 = vb2;
-    vb2 = vb1;
-    vb1 = vbc;
-    b4 = b3;
-    b3 = b2;
-    b2 = b1;
-    b1 = bb;
-    w2 = w1;
-    w1 = w0;
+    if (it >= 7 && (fd < s1 || (last && outD && fd == nD))) a.emf[base + (long long)fd * stD] = e;
+  }
+}
+
+// Lanes policy for B_x: each wave streams whole face rows along x, each row
+// padded by 4 positions before and 4 after.
+template <typename T, int LIM>
+__global__ __launch_bounds__(256) void advect_lanes_kernel(AdvectArgs<T> a) {
+  const Geo& g = a.g;
+  const int t = a.t;  // 1 or 2
+  const int nx = g.n[0];
+  const bool outx = g.bc[0] == 1;
+  const int L = nx + 8;
+  const int ry = g.n[1] + ((t == 1 && g.bc[1] == 1) ? 1 : 0);
+  const int rz = g.n[2] + ((t == 2 && g.bc[2] == 1) ? 1 : 0);
+  const long long nrows = (long long)ry * rz;
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const long long r0 = wave * a.rows_per_wave;
+  if (r0 >= nrows) return;
+  const int rows = (int)min((long long)a.rows_per_wave, nrows - r0);
+  const int npos = rows * L;
+  const int nit = (npos + 63) >> 6;
+  const double dt = a.sc->dt;
+  const T k_half = (T)(dt / (2.0 * g.h[0]));
+  const T k_full = (T)(dt / g.h[0]);
+  AdvectHist<T> h;
+  h.zero();
+  for (int it = 0; it < nit; ++it) {
+    const int q = (it << 6) + lane;
+    const bool valid = q < npos;
+    const int qq = valid ? q : npos - 1;
+    const int rr = qq / L;
+    const int cpos = qq - rr * L - 4;  // cell index along x (-4 .. nx+3)
+    const long long row = r0 + rr;
+    const int y = (int)(row % ry), z = (int)(row / ry);
+    const long long base = (long long)y * g.st[1] + (long long)z * g.st[2];
+    const int ft = (t == 1) ? y : z;
+    const long long st_t = g.st[t];
+    const long long cell_lo = base + (long long)(map_cell(ft - 1, g.n[t], g.bc[t]) - ft) * st_t;
+    const long long cell_hi = base + (long long)(map_cell(ft, g.n[t], g.bc[t]) - ft) * st_t;
+    const int ms = map_cell(cpos, nx, g.bc[0]);
+    const T vlo = a.md[cell_lo + ms] * rcp(a.rho[cell_lo + ms]);
+    const T vhi = a.md[cell_hi + ms] * rcp(a.rho[cell_hi + ms]);
+    const T w0 = T(0.5) * (vlo + vhi);
+    const T bb = a.bt[base + ms];
+    const T b4 = a.bt[base + map_cell(cpos - 4, nx, g.bc[0])];
+    T bn, e;
+    advect_position<T, LIM, LaneHist, true>(w0, bb, b4, k_half, k_full, h, bn, e);
+    const int cb = cpos - 4;
+    if (valid && cb >= 0 && cb < nx) a.bto[base + cb] = bn;
+    const int fd = cpos - 3;
+    if (valid && fd >= 0 && (fd < nx || (outx && fd == nx))) a.emf[base + fd] = e;
   }
 }
 
@@ -365,8 +583,8 @@ __global__ __launch_bounds__(256) void field_constraint_kernel(ConstraintArgs<T>
   const long long up2 = idx + (long long)(map_face(c[T2] + 1, g.n[T2], g.bc[T2]) - c[T2]) * g.st[T2];
   const double dt = a.sc->dt;
   const T dtT = (T)dt;
-  const T h1 = (T)g.h[T1], h2 = (T)g.h[T2];
-  a.bdo[idx] = a.bd[idx] + dtT * ((a.e1[up1] - a.e1[idx]) / h1 + (a.e2[up2] - a.e2[idx]) / h2);
+  const T ih1 = (T)(1.0 / g.h[T1]), ih2 = (T)(1.0 / g.h[T2]);
+  a.bdo[idx] = a.bd[idx] + dtT * ((a.e1[up1] - a.e1[idx]) * ih1 + (a.e2[up2] - a.e2[idx]) * ih2);
 }
 
 // ------------------------------------------------------------ CFL + state check
@@ -378,6 +596,15 @@ struct CheckArgs {
   double gamma;
   Scalars* sc;
 };
+
+__device__ __forceinline__ double fast_speed64(const double* u, const double* b, int d, double gamma, double p,
+                                               double b2) {
+  const double rho = u[0];
+  const double a2 = gamma * p / rho;
+  const double q = a2 + b2 / rho;
+  const double disc = q * q - 4.0 * a2 * b[d] * b[d] / rho;
+  return sqrt(0.5 * (q + sqrt(disc < 0.0 ? 0.0 : disc)));
+}
 
 // Eq. (14)-(15): max over cells and active axes of (|v_d| + c_F,d)/h_d in FP64,
 // plus the state check (rho > 0, p > 0, every value finite).
@@ -407,24 +634,18 @@ __global__ __launch_bounds__(256) void check_cfl_kernel(CheckArgs<T> a) {
     b[1] = 0.5 * ((double)a.b[1][s] + (double)a.b[1][sy]);
     b[2] = 0.5 * ((double)a.b[2][s] + (double)a.b[2][sz]);
     if (!isfinite(b[0]) || !isfinite(b[1]) || !isfinite(b[2])) bad = 1;
-    CellQ<double> q;
-    cell_quantities<double, 0, false>(u, b, a.gamma, q);
-    double p2;
-    const double p = pressure_fp64(u[0], u[1], u[2], u[3], u[4], b[0], b[1], b[2], a.gamma, &p2);
+    const double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    const double m2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+    const double p = (a.gamma - 1.0) * (u[4] - 0.5 * m2 / u[0] - 0.5 * b2);
     if (!(u[0] > 0.0) || !(p > 0.0)) bad = 1;
-    if (g.n[0] > 1) {
-      if (!isfinite(q.d)) bad = 1;
-      cmax = fmax(cmax, (fabs(q.vd) + q.cF) / g.h[0]);
-    }
-    if (g.n[1] > 1) {
-      cell_quantities<double, 1, false>(u, b, a.gamma, q);
-      if (!isfinite(q.d)) bad = 1;
-      cmax = fmax(cmax, (fabs(q.vd) + q.cF) / g.h[1]);
-    }
-    if (g.n[2] > 1) {
-      cell_quantities<double, 2, false>(u, b, a.gamma, q);
-      if (!isfinite(q.d)) bad = 1;
-      cmax = fmax(cmax, (fabs(q.vd) + q.cF) / g.h[2]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (g.n[d] > 1) {
+        const double cf = fast_speed64(u, b, d, a.gamma, p, b2);
+        const double sp = (fabs(u[1 + d] / u[0]) + cf) / g.h[d];
+        if (!isfinite(sp)) bad = 1;
+        cmax = fmax(cmax, sp);
+      }
     }
   }
   // wavefront reduction (64 lanes), then one atomic per wave
@@ -560,6 +781,17 @@ __global__ void diag_final_kernel(const double* partial, int nblocks, double* ou
   out[7] = acc[7] * az;
   out[8] = acc[8];
   out[9] = acc[9];
+}
+
+// Self-test of the lane-shift primitive: out[64*it + lane] = previous
+// position's value of (100*it + lane) over two iterations (128 entries).
+__global__ void lane_shift_selftest_kernel(float* out) {
+  const int lane = threadIdx.x & 63;
+  float carry = -1.0f;
+  for (int it = 0; it < 2; ++it) {
+    const float cur = (float)(100 * it + lane);
+    out[64 * it + lane] = lane_prev(cur, carry);
+  }
 }
 
 }  // namespace fish
