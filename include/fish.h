@@ -82,7 +82,9 @@ typedef struct fish_params {
 typedef struct fish_ctx fish_ctx;
 
 /* Create a context for one box.  *out is NULL on failure.  Validates every
- * field of *p (FISH_ERR_ARG) and allocates the device state (FISH_ERR_NOMEM). */
+ * field of *p (FISH_ERR_ARG) and allocates the device state (FISH_ERR_NOMEM).
+ * Each state array must stay below 4 GiB ((nx+o)(ny+o)(nz+o) elements of 4 or
+ * 8 bytes, o = 1 on outflow axes), else FISH_ERR_UNSUPPORTED. */
 int fish_create(const fish_params* p, fish_ctx** out);
 
 /* Release the context and all its device memory.  NULL is a no-op. */
@@ -133,8 +135,7 @@ size_t fish_device_bytes(const fish_ctx* ctx);
 /* Kernel classes for the timing hook below. */
 enum {
   FISH_KERNEL_FLUID = 1,       /* fluid sweep L_d                          */
-  FISH_KERNEL_ADVECT = 2,      /* field advection of B_d (edge fluxes)     */
-  FISH_KERNEL_CONSTRAINT = 4,  /* constraint update of B_d                 */
+  FISH_KERNEL_FIELD = 2,       /* field sweep B_d (advection + constraint) */
   FISH_KERNEL_CHECK = 8        /* CFL reduction and state check            */
 };
 

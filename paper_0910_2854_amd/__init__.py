@@ -55,7 +55,7 @@ class FishError(RuntimeError):
 EXPORTS = ("fish_create", "fish_destroy", "fish_last_error", "fish_set_state", "fish_get_state",
            "fish_cfl_dt", "fish_strang_step", "fish_sweep", "fish_diagnostics", "fish_device_bytes",
            "fish_timing_enable", "fish_timing_read", "fish_selftest_lane_shift")
-KERNEL_FLUID, KERNEL_ADVECT, KERNEL_CONSTRAINT, KERNEL_CHECK = 1, 2, 4, 8
+KERNEL_FLUID, KERNEL_FIELD, KERNEL_CHECK = 1, 2, 8
 
 _lib = None
 

@@ -42,10 +42,12 @@ struct fish_ctx {
   // state: [buffer][field] with fields rho, mx, my, mz, E, bx, by, bz
   DeviceBuf fields[2][8];
   int cur[8]{};        // current buffer of each field
-  DeviceBuf phi, emf[2], scal, partial, diag_out;
+  DeviceBuf phi, scal, partial, diag_out;
   int npartial = 0;
   int seg[3]{};        // segment length of the streaming sweeps per axis
   bool have_state = false;
+  bool cfl_fresh = false;  // Scalars::cmax_bits holds the CFL speed of the current state
+  bool last_fluid_cfl = false;  // the next x fluid sweep also reduces the CFL speed
   std::string err;
   size_t device_bytes = 0;
   // measurement hook: event pairs around launches of the selected classes
@@ -177,11 +179,16 @@ void launch_fluid(fish_ctx* c) {
   if (D == 0) {
     const long long nrows = (long long)c->n[1] * c->n[2];
     const long long waves = (nrows + a.rows_per_wave - 1) / a.rows_per_wave;
-    hipLaunchKernelGGL((fish::fluid_lanes_kernel<T, GRAV, HSE, LIM>), dim3(grid_for(waves * 64)), dim3(kBlock), 0,
-                       c->stream, a);
+    if (c->last_fluid_cfl)
+      hipLaunchKernelGGL((fish::fluid_lanes_kernel<T, GRAV, HSE, LIM, true>), dim3(grid_for(waves * 64)),
+                         dim3(kBlock), 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((fish::fluid_lanes_kernel<T, GRAV, HSE, LIM, false>), dim3(grid_for(waves * 64)),
+                         dim3(kBlock), 0, c->stream, a);
   } else {
     constexpr int DD = D == 0 ? 1 : D;
-    const long long threads = (long long)c->n[0] * c->n[3 - DD] * a.nseg;
+    const long long pencils = (long long)c->n[0] * c->n[3 - DD];
+    const long long threads = (pencils + 63) / 64 * 64 * a.nseg;
     hipLaunchKernelGGL((fish::fluid_strided_kernel<T, DD, GRAV, HSE, LIM>), dim3(grid_for(threads)), dim3(kBlock),
                        0, c->stream, a);
   }
@@ -209,56 +216,35 @@ int fluid_dispatch(fish_ctx* c) {
 
 template <typename T, int D, int LIM>
 int field_sweep_lim(fish_ctx* c) {
-  const int tt[2] = {(D + 1) % 3, (D + 2) % 3};
-  const Geo g = make_geo(c);
-  const int seg = c->seg[D];
-  const int nseg = (c->n[D] + seg - 1) / seg;
-  for (int s = 0; s < 2; ++s) {
-    const int t = tt[s];
-    fish::AdvectArgs<T> a;
-    a.rho = cur<T>(c, 0);
-    a.md = cur<T>(c, 1 + D);
-    a.bt = cur<T>(c, 5 + t);
-    a.bto = nxt<T>(c, 5 + t);
-    a.emf = static_cast<T*>(c->emf[s].ptr);
-    a.g = g;
-    a.t = t;
-    a.seg = seg;
-    a.nseg = nseg;
-    a.rows_per_wave = rows_per_wave(c->n[0], 4);
-    a.sc = scal(c);
-    {
-      TimedLaunch tl(c, FISH_KERNEL_ADVECT);
-      if (D == 0) {
-        const long long ry = c->n[1] + ((t == 1 && c->p.bc[1] == FISH_OUTFLOW) ? 1 : 0);
-        const long long rz = c->n[2] + ((t == 2 && c->p.bc[2] == FISH_OUTFLOW) ? 1 : 0);
-        const long long waves = (ry * rz + a.rows_per_wave - 1) / a.rows_per_wave;
-        hipLaunchKernelGGL((fish::advect_lanes_kernel<T, LIM>), dim3(grid_for(waves * 64)), dim3(kBlock), 0,
-                           c->stream, a);
-      } else {
-        constexpr int DD = D == 0 ? 1 : D;
-        constexpr int O = 3 - DD;
-        const long long rA = c->n[0] + ((t == 0 && c->p.bc[0] == FISH_OUTFLOW) ? 1 : 0);
-        const long long rO = c->n[O] + ((O == t && c->p.bc[O] == FISH_OUTFLOW) ? 1 : 0);
-        hipLaunchKernelGGL((fish::advect_strided_kernel<T, DD, LIM>), dim3(grid_for(rA * rO * nseg)), dim3(kBlock),
-                           0, c->stream, a);
-      }
-    }
-    int rc = launch_check(c);
-    if (rc) return rc;
-  }
-  fish::ConstraintArgs<T> k;
-  k.bd = cur<T>(c, 5 + D);
-  k.bdo = nxt<T>(c, 5 + D);
-  k.e1 = static_cast<const T*>(c->emf[0].ptr);
-  k.e2 = static_cast<const T*>(c->emf[1].ptr);
-  k.g = g;
-  k.sc = scal(c);
-  long long nf = 1;
-  for (int a2 = 0; a2 < 3; ++a2) nf *= c->n[a2] + ((a2 == D && c->p.bc[a2] == FISH_OUTFLOW) ? 1 : 0);
+  const int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  fish::FieldArgs<T> a;
+  a.rho = cur<T>(c, 0);
+  a.md = cur<T>(c, 1 + D);
+  a.bt[0] = cur<T>(c, 5 + t1);
+  a.bt[1] = cur<T>(c, 5 + t2);
+  a.bd = cur<T>(c, 5 + D);
+  a.bto[0] = nxt<T>(c, 5 + t1);
+  a.bto[1] = nxt<T>(c, 5 + t2);
+  a.bdo = nxt<T>(c, 5 + D);
+  a.g = make_geo(c);
+  a.seg = c->seg[D];
+  a.nseg = (c->n[D] + a.seg - 1) / a.seg;
+  a.rows_per_wave = rows_per_wave(c->n[0], 4);
+  a.sc = scal(c);
   {
-    TimedLaunch tl(c, FISH_KERNEL_CONSTRAINT);
-    hipLaunchKernelGGL((fish::field_constraint_kernel<T, D>), dim3(grid_for(nf)), dim3(kBlock), 0, c->stream, k);
+    TimedLaunch tl(c, FISH_KERNEL_FIELD);
+    if (D == 0) {
+      const long long rows = (long long)(c->n[1] + c->o[1]) * (c->n[2] + c->o[2]);
+      const long long waves = (rows + a.rows_per_wave - 1) / a.rows_per_wave;
+      hipLaunchKernelGGL((fish::field_lanes_kernel<T, LIM>), dim3(grid_for(waves * 64)), dim3(kBlock), 0, c->stream,
+                         a);
+    } else {
+      constexpr int DD = D == 0 ? 1 : D;
+      const long long rows = (long long)(c->n[0] + c->o[0]) * (c->n[3 - DD] + c->o[3 - DD]);
+      const long long threads = (rows + 63) / 64 * 64 * a.nseg;
+      hipLaunchKernelGGL((fish::field_strided_kernel<T, DD, LIM>), dim3(grid_for(threads)), dim3(kBlock), 0,
+                         c->stream, a);
+    }
   }
   for (int f = 5; f < 8; ++f) c->cur[f] = 1 - c->cur[f];
   return launch_check(c);
@@ -308,7 +294,9 @@ int launch_check_cfl(fish_ctx* c) {
 }
 
 int check_cfl(fish_ctx* c) {
-  return c->prec == FISH_FP64 ? launch_check_cfl<double>(c) : launch_check_cfl<float>(c);
+  int rc = c->prec == FISH_FP64 ? launch_check_cfl<double>(c) : launch_check_cfl<float>(c);
+  if (rc == FISH_OK) c->cfl_fresh = true;
+  return rc;
 }
 
 template <typename T>
@@ -477,6 +465,11 @@ int fish_create(const fish_params* p, fish_ctx** out) {
   c->st[1] = c->ext[0];
   c->st[2] = c->ext[0] * c->ext[1];
   c->nelem = (size_t)(c->ext[0] * c->ext[1] * c->ext[2]);
+  if (c->nelem * c->esize >= (1ull << 32)) {
+    // the kernels address each array with 32-bit byte offsets
+    delete c;
+    return FISH_ERR_UNSUPPORTED;
+  }
   int rc = set_device(c);
   if (rc) {
     delete c;
@@ -486,7 +479,6 @@ int fish_create(const fish_params* p, fish_ctx** out) {
   for (int b = 0; b < 2 && rc == FISH_OK; ++b)
     for (int f = 0; f < 8 && rc == FISH_OK; ++f) rc = dev_alloc(c, c->fields[b][f], bytes);
   if (rc == FISH_OK && p->gravity) rc = dev_alloc(c, c->phi, bytes);
-  for (int s = 0; s < 2 && rc == FISH_OK; ++s) rc = dev_alloc(c, c->emf[s], bytes);
   if (rc == FISH_OK) rc = dev_alloc(c, c->scal, sizeof(Scalars));
   c->npartial = (int)std::min<long long>(1024, std::max<long long>(1, cells / 4096));
   if (rc == FISH_OK) rc = dev_alloc(c, c->partial, (size_t)c->npartial * 10 * sizeof(double));
@@ -518,8 +510,6 @@ void fish_destroy(fish_ctx* c) {
   for (int b = 0; b < 2; ++b)
     for (int f = 0; f < 8; ++f) dev_free(c, c->fields[b][f]);
   dev_free(c, c->phi);
-  dev_free(c, c->emf[0]);
-  dev_free(c, c->emf[1]);
   dev_free(c, c->scal);
   dev_free(c, c->partial);
   dev_free(c, c->diag_out);
@@ -569,7 +559,8 @@ int fish_cfl_dt(fish_ctx* c, double* dt_out) {
   if (!c->have_state) return fail(c, FISH_ERR_ARG, "no state");
   int rc = set_device(c);
   if (rc) return rc;
-  if ((rc = check_cfl(c))) return rc;
+  if (!c->cfl_fresh && (rc = check_cfl(c))) return rc;
+  c->cfl_fresh = true;
   Scalars s;
   if ((rc = read_scalars(c, &s))) return rc;
   if (s.status) return fail(c, FISH_ERR_STATE, "CFL found rho <= 0, p <= 0 or a non-finite value");
@@ -592,6 +583,7 @@ int fish_sweep(fish_ctx* c, int op, int dir, double dt) {
   if (rc) return rc;
   hipLaunchKernelGGL(fish::set_dt_kernel, dim3(1), dim3(1), 0, c->stream, scal(c), dt);
   if ((rc = launch_check(c))) return rc;
+  c->cfl_fresh = false;
   return run_sub(c, op, dir);
 }
 
@@ -602,23 +594,35 @@ int fish_strang_step(fish_ctx* c, double dt) {
   int rc = set_device(c);
   if (rc) return rc;
   if (dt == 0.0) {
-    if ((rc = check_cfl(c))) return rc;
+    // the CFL speed of the current state is left by the previous step's last
+    // sweep (or by set_state); otherwise reduce it now
+    if (!c->cfl_fresh && (rc = check_cfl(c))) return rc;
     hipLaunchKernelGGL(fish::finalize_dt_kernel, dim3(1), dim3(1), 0, c->stream, scal(c), c->p.cfl);
   } else {
     hipLaunchKernelGGL(fish::set_dt_kernel, dim3(1), dim3(1), 0, c->stream, scal(c), dt);
   }
   if ((rc = launch_check(c))) return rc;
+  c->cfl_fresh = false;
   // Eqs. (12)-(13), symmetric order
   for (int d = 0; d < 3; ++d) {
     if ((rc = run_sub(c, 0, d))) return rc;
     if ((rc = run_sub(c, 1, d))) return rc;
   }
-  for (int d = 2; d >= 0; --d) {
+  for (int d = 2; d >= 1; --d) {
     if ((rc = run_sub(c, 1, d))) return rc;
     if ((rc = run_sub(c, 0, d))) return rc;
   }
+  if ((rc = run_sub(c, 1, 0))) return rc;
+  // the last sub-operator also reduces the CFL speed of the new state
+  hipLaunchKernelGGL(fish::reset_cmax_kernel, dim3(1), dim3(1), 0, c->stream, scal(c));
+  c->last_fluid_cfl = true;
+  rc = run_sub(c, 0, 0);
+  c->last_fluid_cfl = false;
+  if (rc) return rc;
   hipLaunchKernelGGL(fish::advance_time_kernel, dim3(1), dim3(1), 0, c->stream, scal(c));
-  return launch_check(c);
+  if ((rc = launch_check(c))) return rc;
+  c->cfl_fresh = true;
+  return FISH_OK;
 }
 
 int fish_diagnostics(fish_ctx* c, double* out10) {

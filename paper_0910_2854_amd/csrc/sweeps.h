@@ -42,14 +42,29 @@ struct Scalars {
   int pad;
 };
 
+// ------------------------------------------------------------ addressing
+// Load/store at a wave-uniform base pointer plus a 32-bit per-lane byte
+// offset (the scalar-base + vector-offset form of the global memory
+// instructions: no 64-bit address arithmetic per lane).
+template <typename T>
+__device__ __forceinline__ T ld(const T* p, unsigned off_bytes) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + off_bytes);
+}
+template <typename T>
+__device__ __forceinline__ void st(T* p, unsigned off_bytes, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + off_bytes) = v;
+}
+
 // ------------------------------------------------------------ position history
-// prev(cur, h): the value this quantity had one stream position earlier.
+// prev(cur, hin, hout): the value this quantity had one stream position
+// earlier, read from the history hin; the history for the next position is
+// written to hout.  The kernels alternate two history sets (hin/hout swap
+// every position), so no register is copied to move the window.
 struct StridedHist {
   template <typename V>
-  __device__ __forceinline__ static V prev(const V& cur, V& h) {
-    V p = h;
-    h = cur;
-    return p;
+  __device__ __forceinline__ static V prev(const V& cur, const V& hin, V& hout) {
+    hout = cur;
+    return hin;
   }
 };
 
@@ -78,25 +93,30 @@ __device__ __forceinline__ double lane_prev(double cur, double& carry) {
 
 struct LaneHist {
   template <typename T>
-  __device__ __forceinline__ static T prev(const T& cur, T& h) {
-    return lane_prev(cur, h);
+  __device__ __forceinline__ static T prev(const T& cur, const T& hin, T& hout) {
+    T c = hin;
+    const T o = lane_prev(cur, c);
+    hout = c;
+    return o;
   }
   template <typename T, bool HSE>
-  __device__ __forceinline__ static CellQ<T, HSE> prev(const CellQ<T, HSE>& cur, CellQ<T, HSE>& h) {
+  __device__ __forceinline__ static CellQ<T, HSE> prev(const CellQ<T, HSE>& cur, const CellQ<T, HSE>& hin,
+                                                       CellQ<T, HSE>& hout) {
     CellQ<T, HSE> o;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      o.u[k] = lane_prev(cur.u[k], h.u[k]);
-      o.F[k] = lane_prev(cur.F[k], h.F[k]);
+      o.u[k] = prev(cur.u[k], hin.u[k], hout.u[k]);
+      o.F[k] = prev(cur.F[k], hin.F[k], hout.F[k]);
     }
-    o.d = lane_prev(cur.d, h.d);
+    o.d = prev(cur.d, hin.d, hout.d);
     if (HSE) {
-      o.vd = lane_prev(cur.vd, h.vd);
-      o.cF = lane_prev(cur.cF, h.cF);
-      o.cS = lane_prev(cur.cS, h.cS);
-      o.xiE = lane_prev(cur.xiE, h.xiE);
+      o.vd = prev(cur.vd, hin.vd, hout.vd);
+      o.cF = prev(cur.cF, hin.cF, hout.cF);
+      o.cS = prev(cur.cS, hin.cS, hout.cS);
+      o.xiE = prev(cur.xiE, hin.xiE, hout.xiE);
     } else {
       o.vd = o.cF = o.cS = o.xiE = T(0);
+      hout.vd = hout.cF = hout.cS = hout.xiE = T(0);
     }
     return o;
   }
@@ -107,11 +127,63 @@ struct Vec {
   T v[N];
 };
 template <typename H, typename T, int N>
-__device__ __forceinline__ Vec<T, N> prev_vec(const Vec<T, N>& cur, Vec<T, N>& h) {
+__device__ __forceinline__ Vec<T, N> prev_vec(const Vec<T, N>& cur, const Vec<T, N>& hin, Vec<T, N>& hout) {
   Vec<T, N> o;
 #pragma unroll
-  for (int k = 0; k < N; ++k) o.v[k] = H::prev(cur.v[k], h.v[k]);
+  for (int k = 0; k < N; ++k) o.v[k] = H::prev(cur.v[k], hin.v[k], hout.v[k]);
   return o;
+}
+
+// ------------------------------------------------------------ lanes cursor
+// Position of one lane in the stream of whole rows a wave walks (lanes
+// policy): row rr of the wave's rows and position cp in [0, L) of that row.
+// Advancing by one iteration moves 64 positions; the row indices (y, z) are
+// stepped, never divided, and stay on the wave's last row past its end (those
+// lanes' positions are beyond the stream and write nothing).
+struct RowCursor {
+  int cp, rr, y, z;
+  bool moved;
+  __device__ void init(int lane, int L, long long r0, int rows, int ny) {
+    cp = lane;
+    rr = 0;
+    while (cp >= L && rr < rows - 1) {
+      cp -= L;
+      ++rr;
+    }
+    const long long row = r0 + rr;
+    y = (int)(row % ny);
+    z = (int)(row / ny);
+    moved = true;
+  }
+  __device__ void advance(int L, int rows, int ny) {
+    cp += 64;
+    moved = false;
+    while (cp >= L && rr < rows - 1) {
+      cp -= L;
+      ++rr;
+      if (++y == ny) {
+        y = 0;
+        ++z;
+      }
+      moved = true;
+    }
+  }
+};
+
+// Cheap wrap for indices within one period of the box (the slow path only
+// for boxes thinner than the stencil halo).
+__device__ __forceinline__ int map_cell_near(int i, int n, int bc) {
+  if (i >= 0 && i < n) return i;
+  if (bc == 0) {
+    if (i < 0 && i + n >= 0) return i + n;
+    if (i >= n && i - n < n) return i - n;
+    return wrap(i, n);
+  }
+  return i < 0 ? 0 : n - 1;
+}
+__device__ __forceinline__ int map_face_near(int i, int n, int bc) {
+  if (bc == 0) return map_cell_near(i, n, 0);
+  return i < 0 ? 0 : (i > n ? n : i);
 }
 
 // ------------------------------------------------------------ L_d pipeline
@@ -171,18 +243,19 @@ struct FluidHist {
 // caller reloads it (lanes policy); otherwise the history chain supplies it.
 template <typename T, int D, bool GRAV, bool HSE, int LIM, typename H, bool RELOAD_U3>
 __device__ __forceinline__ void fluid_position(const T* uc, const Vec<T, 3>& bcc, T phc, const T* u3_loaded,
-                                               const FluidConsts<T>& k, FluidHist<T, HSE>& h, T* un) {
+                                               const FluidConsts<T>& k, const FluidHist<T, HSE>& hi,
+                                               FluidHist<T, HSE>& ho, T* un) {
   // cell quantities of u at c and c-1
   CellQ<T, HSE> q0;
   cell_quantities<T, D, HSE>(uc, bcc.v, k.gamma, q0);
-  const CellQ<T, HSE> q0m = H::prev(q0, h.q0);
-  const Vec<T, 3> bcm = prev_vec<H>(bcc, h.bc);
+  const CellQ<T, HSE> q0m = H::prev(q0, hi.q0, ho.q0);
+  const Vec<T, 3> bcm = prev_vec<H>(bcc, hi.bc, ho.bc);
   T phm1 = T(0), phm2 = T(0), phm3 = T(0), phm4 = T(0);
   if (GRAV || HSE) {
-    phm1 = H::prev(phc, h.ph1);
-    phm2 = H::prev(phm1, h.ph2);
-    phm3 = H::prev(phm2, h.ph3);
-    phm4 = H::prev(phm3, h.ph4);
+    phm1 = H::prev(phc, hi.ph1, ho.ph1);
+    phm2 = H::prev(phm1, hi.ph2, ho.ph2);
+    phm3 = H::prev(phm2, hi.ph3, ho.ph3);
+    phm4 = H::prev(phm3, hi.ph4, ho.ph4);
   }
   // predictor flux at interface c-1/2 (Eq. 24, dissipation scaled by alpha)
   T Q[5];
@@ -190,7 +263,7 @@ __device__ __forceinline__ void fluid_position(const T* uc, const Vec<T, 3>& bcc
   dissipation<T, HSE>(q0m, q0, phm1, phc, Q);
 #pragma unroll
   for (int i = 0; i < 5; ++i) F1.v[i] = T(0.5) * (q0m.F[i] + q0.F[i]) - k.halfalpha * Q[i];
-  const Vec<T, 5> F1m = prev_vec<H>(F1, h.F1);
+  const Vec<T, 5> F1m = prev_vec<H>(F1, hi.F1, ho.F1);
   // predictor half step of cell c-1 (Eq. 41)
   T up[5];
   if (GRAV) {
@@ -205,7 +278,7 @@ __device__ __forceinline__ void fluid_position(const T* uc, const Vec<T, 3>& bcc
   // cell quantities of the half-step state of c-1 (field unchanged), and of c-2
   CellQ<T, HSE> q1;
   cell_quantities<T, D, HSE>(up, bcm.v, k.gamma, q1);
-  const CellQ<T, HSE> q1m = H::prev(q1, h.q1);
+  const CellQ<T, HSE> q1m = H::prev(q1, hi.q1, ho.q1);
   // relaxed flux differences across interface c-3/2 (between c-2 and c-1)
   T Qc[5];
   Vec<T, 5> ap, am, bs;
@@ -217,17 +290,17 @@ __device__ __forceinline__ void fluid_position(const T* uc, const Vec<T, 3>& bcc
     am.v[i] = T(0.5) * (dF - Qc[i]);
     bs.v[i] = T(0.5) * (q1m.F[i] + q1.F[i]) - T(0.5) * Qc[i];
   }
-  const Vec<T, 5> apm = prev_vec<H>(ap, h.ap);
-  const Vec<T, 5> amm = prev_vec<H>(am, h.am);
-  const Vec<T, 5> bsm = prev_vec<H>(bs, h.bs);
+  const Vec<T, 5> apm = prev_vec<H>(ap, hi.ap, ho.ap);
+  const Vec<T, 5> amm = prev_vec<H>(am, hi.am, ho.am);
+  const Vec<T, 5> bsm = prev_vec<H>(bs, hi.bs, ho.bs);
   // limited second-order flux at interface c-5/2 (Eq. 34)
   Vec<T, 5> Lp, F2;
 #pragma unroll
   for (int i = 0; i < 5; ++i) Lp.v[i] = limit<T, LIM>(apm.v[i], ap.v[i]);
-  const Vec<T, 5> Lpm = prev_vec<H>(Lp, h.Lp);
+  const Vec<T, 5> Lpm = prev_vec<H>(Lp, hi.Lp, ho.Lp);
 #pragma unroll
   for (int i = 0; i < 5; ++i) F2.v[i] = bsm.v[i] + T(0.5) * (Lpm.v[i] - limit<T, LIM>(amm.v[i], am.v[i]));
-  const Vec<T, 5> F2m = prev_vec<H>(F2, h.F2);
+  const Vec<T, 5> F2m = prev_vec<H>(F2, hi.F2, ho.F2);
   // state of cell c-3 before the sweep
   T u3[5];
   if (RELOAD_U3) {
@@ -237,17 +310,17 @@ __device__ __forceinline__ void fluid_position(const T* uc, const Vec<T, 3>& bcc
     Vec<T, 5> um1;
 #pragma unroll
     for (int i = 0; i < 5; ++i) um1.v[i] = q0m.u[i];
-    const Vec<T, 5> um2 = prev_vec<H>(um1, h.ua);
-    const Vec<T, 5> um3 = prev_vec<H>(um2, h.ub);
+    const Vec<T, 5> um2 = prev_vec<H>(um1, hi.ua, ho.ua);
+    const Vec<T, 5> um3 = prev_vec<H>(um2, hi.ub, ho.ub);
 #pragma unroll
     for (int i = 0; i < 5; ++i) u3[i] = um3.v[i];
   }
   // corrector of cell c-3 (Eq. 43)
   if (GRAV) {
-    const T rpm2 = H::prev(up[RHO], h.rp1);   // rho' of c-2
-    const T rpm3 = H::prev(rpm2, h.rp2);      // rho' of c-3
-    const T mpm2 = H::prev(up[MX + D], h.mp1);
-    const T mpm3 = H::prev(mpm2, h.mp2);
+    const T rpm2 = H::prev(up[RHO], hi.rp1, ho.rp1);   // rho' of c-2
+    const T rpm3 = H::prev(rpm2, hi.rp2, ho.rp2);      // rho' of c-3
+    const T mpm2 = H::prev(up[MX + D], hi.mp1, ho.mp1);
+    const T mpm3 = H::prev(mpm2, hi.mp2, ho.mp2);
     T S[5];
     gravity_source<T, D>(rpm3, mpm3, phm2 - phm4, k.inv2h, S);
 #pragma unroll
@@ -274,7 +347,22 @@ __device__ __forceinline__ FluidConsts<T> fluid_consts(const FluidArgs<T>& a, in
   return k;
 }
 
-// Strided policy (D = y or z): one thread per pencil segment.
+// Strided policy: wave w walks segment sg of 64 pencils.  The segment (hence
+// every position and its boundary mapping along d) is uniform across the wave
+// and lives in scalar registers; each lane only adds its pencil offset.
+// Returns false for waves beyond the grid (the whole wave exits together).
+__device__ __forceinline__ bool strided_map(int P, int nseg, int& sg, int& p, bool& active) {
+  const int wps = (P + 63) >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  sg = wave / wps;
+  if (sg >= nseg) return false;
+  const int p0 = (wave - sg * wps) * 64 + (int)(threadIdx.x & 63);
+  active = p0 < P;
+  p = active ? p0 : P - 1;
+  return true;
+}
+
+// Strided policy (D = y or z): one lane per pencil segment, lanes along x.
 template <typename T, int D, bool GRAV, bool HSE, int LIM>
 __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidArgs<T> a) {
   static_assert(D != 0, "x sweeps use the lanes policy");
@@ -283,54 +371,120 @@ __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidArgs<T> a) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   const Geo& g = a.g;
   const int nA = g.n[A], nO = g.n[O], nD = g.n[D];
-  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long total = (long long)nA * nO * a.nseg;
-  if (tid >= total) return;
-  const int ia = (int)(tid % nA);
-  const long long r = tid / nA;
-  const int io = (int)(r % nO);
-  const int sg = (int)(r / nO);
+  int sg, p;
+  bool active;
+  if (!strided_map(nA * nO, a.nseg, sg, p, active)) return;
   const int s0 = sg * a.seg;
   const int s1 = min(nD, s0 + a.seg);
   int c[3];
-  c[A] = ia;
-  c[O] = io;
+  c[A] = p % nA;
+  c[O] = p / nA;
   c[D] = 0;
   const long long stD = g.st[D];
-  const long long base = (long long)c[A] * g.st[A] + (long long)c[O] * g.st[O];
-  const long long hi1 = base + (long long)(map_face(c[T1] + 1, g.n[T1], g.bc[T1]) - c[T1]) * g.st[T1];
-  const long long hi2 = base + (long long)(map_face(c[T2] + 1, g.n[T2], g.bc[T2]) - c[T2]) * g.st[T2];
+  const int bcD = g.bc[D];
+  // lane byte offsets (every array is below 4 GiB)
+  const long long lbase = (long long)c[A] * g.st[A] + (long long)c[O] * g.st[O];
+  const unsigned base = (unsigned)(lbase * (long long)sizeof(T));
+  const unsigned hi1 = (unsigned)((lbase + (long long)(map_face(c[T1] + 1, g.n[T1], g.bc[T1]) - c[T1]) * g.st[T1]) *
+                                  (long long)sizeof(T));
+  const unsigned hi2 = (unsigned)((lbase + (long long)(map_face(c[T2] + 1, g.n[T2], g.bc[T2]) - c[T2]) * g.st[T2]) *
+                                  (long long)sizeof(T));
   const FluidConsts<T> k = fluid_consts(a, D);
-  FluidHist<T, HSE> h;
-  h.zero();
-  const int npos = (s1 - s0) + 6;
-#pragma unroll 2
-  for (int it = 0; it < npos; ++it) {
+  FluidHist<T, HSE> hA, hB;
+  hA.zero();
+  hB.zero();
+  struct In {
+    T u[5];
+    Vec<T, 3> bc;
+    T phi;
+  };
+  // inputs of position it (loads only: issued one position ahead of use)
+  auto load = [&](int it) {
+    In in;
+    const int s = s0 - 3 + it;  // uniform
+    const long long off = (long long)map_cell(s, nD, bcD) * stD;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) in.u[i] = ld(a.u[i] + off, base);
+    const T* bD0 = a.b[D] + (long long)map_face(s, nD, bcD) * stD;
+    const T* bD1 = a.b[D] + (long long)map_face(s + 1, nD, bcD) * stD;
+    const T* b1 = a.b[T1] + off;
+    const T* b2 = a.b[T2] + off;
+    in.bc.v[D] = T(0.5) * (ld(bD0, base) + ld(bD1, base));
+    in.bc.v[T1] = T(0.5) * (ld(b1, base) + ld(b1, hi1));
+    in.bc.v[T2] = T(0.5) * (ld(b2, base) + ld(b2, hi2));
+    in.phi = GRAV ? load_phi(a.phi, lbase, stD, s, nD, bcD) : T(0);
+    return in;
+  };
+  auto compute = [&](int it, const In& in, const FluidHist<T, HSE>& hi, FluidHist<T, HSE>& ho) {
     const int s = s0 - 3 + it;
-    const long long off = (long long)map_cell(s, nD, g.bc[D]) * stD;
-    T uc[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) uc[i] = a.u[i][base + off];
-    Vec<T, 3> bcc;
-    const long long f0 = (long long)map_face(s, nD, g.bc[D]) * stD;
-    const long long f1 = (long long)map_face(s + 1, nD, g.bc[D]) * stD;
-    bcc.v[D] = T(0.5) * (a.b[D][base + f0] + a.b[D][base + f1]);
-    bcc.v[T1] = T(0.5) * (a.b[T1][base + off] + a.b[T1][hi1 + off]);
-    bcc.v[T2] = T(0.5) * (a.b[T2][base + off] + a.b[T2][hi2 + off]);
-    T phc = T(0);
-    if (GRAV) phc = load_phi(a.phi, base, stD, s, nD, g.bc[D]);
     T un[5];
-    fluid_position<T, D, GRAV, HSE, LIM, StridedHist, false>(uc, bcc, phc, nullptr, k, h, un);
-    if (it >= 6) {
-      const long long o = base + (long long)(s - 3) * stD;
+    fluid_position<T, D, GRAV, HSE, LIM, StridedHist, false>(in.u, in.bc, in.phi, nullptr, k, hi, ho, un);
+    if (it >= 6 && s - 3 < s1 && active) {
+      const long long o = (long long)(s - 3) * stD;
 #pragma unroll
-      for (int i = 0; i < 5; ++i) a.uo[i][o] = un[i];
+      for (int i = 0; i < 5; ++i) st(a.uo[i] + o, base, un[i]);
     }
+  };
+  // positions s0-3 .. s1+2, padded to an even count (the pad writes nothing;
+  // the prefetch reads at most two positions past the end, mapped in range)
+  const int npos = (s1 - s0) + 6;
+  In cur = load(0);
+  for (int it = 0; it < npos; it += 2) {
+    const In nxt = load(it + 1);
+    compute(it, cur, hA, hB);
+    cur = load(it + 2);
+    compute(it + 1, nxt, hB, hA);
   }
 }
 
-// Lanes policy (D = x): each wave streams rows_per_wave whole x rows.
-template <typename T, bool GRAV, bool HSE, int LIM>
+// CFL speed of one cell for Eq. (14)-(15): max over active axes of
+// (|v_d| + c_F,d)/h_d, with the pressure recovered in FP64; also flags a bad
+// state (rho <= 0, p <= 0 or a non-finite value).
+template <typename T>
+__device__ __forceinline__ double cell_cfl_speed(const T* u, const T* b, double gamma, const Geo& g, int& bad) {
+  T b2;
+  const T p = pressure<T>(u, b, gamma - 1.0, &b2);
+  const T ri = rcp(u[RHO]);
+  const T a2 = (T)gamma * p * ri;
+  const T q = a2 + b2 * ri;
+  double cmax = 0.0;
+  bool ok = u[RHO] > T(0) && p > T(0);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) ok = ok && isfinite(u[i]);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (g.n[d] > 1) {
+      const T disc = q * q - T(4) * a2 * b[d] * b[d] * ri;
+      const T cf = fsqrt(T(0.5) * (q + fsqrt(disc < T(0) ? T(0) : disc)));
+      const double sp = ((double)fabs(u[MX + d] * ri) + (double)cf) / g.h[d];
+      ok = ok && isfinite(sp);
+      cmax = fmax(cmax, sp);
+    }
+  }
+  if (!ok) bad = 1;
+  return cmax;
+}
+
+// Reduce (cmax, bad) over the wave and publish with one atomic per wave.
+// Every lane of the wave must reach this call.
+__device__ __forceinline__ void publish_cfl(double cmax, int bad, Scalars* sc) {
+  unsigned long long bits = __double_as_longlong(cmax);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(bits, off, 64);
+    bits = o > bits ? o : bits;
+    bad |= __shfl_xor(bad, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&sc->cmax_bits, bits);
+    if (bad) atomicOr(&sc->status, 1);
+  }
+}
+
+// Lanes policy (D = x): each wave streams rows_per_wave whole x rows.  With
+// CFL the sweep also reduces the CFL speed of the state it writes (the last
+// sub-operator of a double step leaves the next step's time step ready).
+template <typename T, bool GRAV, bool HSE, int LIM, bool CFL>
 __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidArgs<T> a) {
   constexpr int D = 0;
   const Geo& g = a.g;
@@ -345,246 +499,420 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidArgs<T> a) {
   const int npos = rows * L;
   const int nit = (npos + 63) >> 6;
   const FluidConsts<T> k = fluid_consts(a, D);
-  FluidHist<T, HSE> h;
-  h.zero();
-  for (int it = 0; it < nit; ++it) {
-    const int q = (it << 6) + lane;
-    const bool valid = q < npos;
-    const int qq = valid ? q : npos - 1;
-    const int rr = qq / L;
-    const int cpos = qq - rr * L - 3;        // cell index along x (-3 .. nx+2)
-    const long long row = r0 + rr;
-    const int y = (int)(row % ny), z = (int)(row / ny);
-    const long long base = (long long)y * g.st[1] + (long long)z * g.st[2];
-    const long long yhi = base + (long long)(map_face(y + 1, ny, g.bc[1]) - y) * g.st[1];
-    const long long zhi = base + (long long)(map_face(z + 1, nz, g.bc[2]) - z) * g.st[2];
-    const int ms = map_cell(cpos, nx, g.bc[0]);
-    T uc[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) uc[i] = a.u[i][base + ms];
-    Vec<T, 3> bcc;
-    bcc.v[0] = T(0.5) * (a.b[0][base + map_face(cpos, nx, g.bc[0])] + a.b[0][base + map_face(cpos + 1, nx, g.bc[0])]);
-    bcc.v[1] = T(0.5) * (a.b[1][base + ms] + a.b[1][yhi + ms]);
-    bcc.v[2] = T(0.5) * (a.b[2][base + ms] + a.b[2][zhi + ms]);
-    T phc = T(0);
-    if (GRAV) phc = load_phi(a.phi, base, 1, cpos, nx, g.bc[0]);
-    const int m3 = map_cell(cpos - 3, nx, g.bc[0]);
-    T u3[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) u3[i] = a.u[i][base + m3];
-    T un[5];
-    fluid_position<T, D, GRAV, HSE, LIM, LaneHist, true>(uc, bcc, phc, u3, k, h, un);
-    const int co = cpos - 3;
-    if (valid && co >= 0 && co < nx) {
-#pragma unroll
-      for (int i = 0; i < 5; ++i) a.uo[i][base + co] = un[i];
+  FluidHist<T, HSE> hA, hB;
+  hA.zero();
+  hB.zero();
+  double cmax = 0.0;
+  int bad = 0;
+  RowCursor rc;
+  rc.init(lane, L, r0, rows, ny);
+  unsigned base = 0, dy = 0, dz = 0;  // row offsets (elements; arrays < 2^31 elements)
+  constexpr unsigned z4 = sizeof(T);
+  struct In {
+    T u[5], u3[5];
+    Vec<T, 3> bc;
+    T phi;
+    T b3[3];      // cell-centred field of the output cell (CFL only)
+    unsigned o3;  // byte offset of the output cell c-3
+    int co;       // output cell index along x
+    bool valid;
+  };
+  // inputs of the lane's next stream position (loads only, one iteration ahead)
+  auto load = [&](int it) {
+    if (rc.moved) {
+      const int y = rc.y, z = rc.z;
+      base = (unsigned)((long long)y * g.st[1] + (long long)z * g.st[2]);
+      dy = (unsigned)((long long)(map_face_near(y + 1, ny, g.bc[1]) - y) * g.st[1]) * z4;
+      dz = (unsigned)((long long)(map_face_near(z + 1, nz, g.bc[2]) - z) * g.st[2]) * z4;
     }
+    In in;
+    in.valid = (it << 6) + lane < npos;
+    const int cpos = rc.cp - 3;  // cell index along x (-3 .. nx+2)
+    in.co = cpos - 3;
+    const unsigned ms = (base + (unsigned)map_cell_near(cpos, nx, g.bc[0])) * z4;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) in.u[i] = ld(a.u[i], ms);
+    const unsigned f0 = (base + (unsigned)map_face_near(cpos, nx, g.bc[0])) * z4;
+    const unsigned f1 = (base + (unsigned)map_face_near(cpos + 1, nx, g.bc[0])) * z4;
+    in.bc.v[0] = T(0.5) * (ld(a.b[0], f0) + ld(a.b[0], f1));
+    in.bc.v[1] = T(0.5) * (ld(a.b[1], ms) + ld(a.b[1], ms + dy));
+    in.bc.v[2] = T(0.5) * (ld(a.b[2], ms) + ld(a.b[2], ms + dz));
+    in.phi = GRAV ? load_phi(a.phi, (long long)base, 1, cpos, nx, g.bc[0]) : T(0);
+    in.o3 = (base + (unsigned)map_cell_near(cpos - 3, nx, g.bc[0])) * z4;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) in.u3[i] = ld(a.u[i], in.o3);
+    if (CFL) {
+      const unsigned g0 = (base + (unsigned)map_face_near(cpos - 3, nx, g.bc[0])) * z4;
+      const unsigned g1 = (base + (unsigned)map_face_near(cpos - 2, nx, g.bc[0])) * z4;
+      in.b3[0] = T(0.5) * (ld(a.b[0], g0) + ld(a.b[0], g1));
+      in.b3[1] = T(0.5) * (ld(a.b[1], in.o3) + ld(a.b[1], in.o3 + dy));
+      in.b3[2] = T(0.5) * (ld(a.b[2], in.o3) + ld(a.b[2], in.o3 + dz));
+    }
+    rc.advance(L, rows, ny);
+    return in;
+  };
+  auto compute = [&](const In& in, const FluidHist<T, HSE>& hi, FluidHist<T, HSE>& ho) {
+    T un[5];
+    fluid_position<T, D, GRAV, HSE, LIM, LaneHist, true>(in.u, in.bc, in.phi, in.u3, k, hi, ho, un);
+    const bool out = in.valid && in.co >= 0 && in.co < nx;
+    if (out) {
+#pragma unroll
+      for (int i = 0; i < 5; ++i) st(a.uo[i], in.o3, un[i]);
+    }
+    if (CFL) {
+      int cell_bad = 0;
+      const double sp = cell_cfl_speed<T>(un, in.b3, a.gamma, g, cell_bad);
+      if (out) {
+        cmax = fmax(cmax, sp);
+        bad |= cell_bad;
+      }
+    }
+  };
+  In cur = load(0);
+  for (int it = 0; it < nit; it += 2) {
+    const In nxt = load(it + 1);
+    compute(cur, hA, hB);
+    cur = load(it + 2);
+    compute(nxt, hB, hA);
   }
+  if (CFL) publish_cfl(cmax, bad, const_cast<Scalars*>(a.sc));
 }
 
-// ------------------------------------------------------------ B_d, advection
+// ------------------------------------------------------------ B_d (fused)
+// One kernel per field sweep: the transverse advection of b_t1 and b_t2 and
+// the constraint update of b_d from the same edge fluxes (Eq. 64), without
+// an edge-flux array in HBM.  A thread owns the face rows (t1-face c1, t2-cell
+// c2) of b_t1, (t1-cell c1, t2-face c2) of b_t2 and (c1, c2) of b_d; the edge
+// fluxes of the neighbouring rows c1+1 and c2+1 that the constraint needs are
+// recomputed from the same inputs (bitwise the values their owners compute).
 template <typename T>
-struct AdvectArgs {
+struct FieldArgs {
   const T* rho;
-  const T* md;    // momentum along d
-  const T* bt;    // transverse face field b_t (input)
-  T* bto;         // b_t output
-  T* emf;         // edge flux output, layout of the fields
+  const T* md;             // momentum along d (the fluid state is held fixed)
+  const T* bt[2];          // b_t1, b_t2 (input)
+  const T* bd;             // b_d (input)
+  T* bto[2];               // outputs
+  T* bdo;
   Geo g;
-  int t;          // transverse axis
-  int seg, nseg;
-  int rows_per_wave;
+  int seg, nseg;           // strided policy
+  int rows_per_wave;       // lanes policy
   const Scalars* sc;
 };
 
 template <typename T>
-struct AdvectHist {
+struct RowHist {
   T w1, w2, b1, b2, b3, b4, f2, p1, vb1, vb2, vb3, fp3, fp4, fp5, P2;
   __device__ void zero() { w1 = w2 = b1 = b2 = b3 = b4 = f2 = p1 = vb1 = vb2 = vb3 = fp3 = fp4 = fp5 = P2 = T(0); }
 };
 
-// One position of one face row of b_t along D: Eq. (65) face velocity w0 at
+// One position of one face row of b_t along d: Eq. (65) face velocity w0 at
 // cell c, Eq. (66) smoothing, Eq. (68) interface velocity, Eq. (67)
 // first-order upwind predictor flux, second-order limited upwind corrector
-// flux (end of Sect. 2.4), Eq. (63).  Outputs the new b_t of cell c-4 and
-// the edge flux at d-face c-3 (the interface between c-4 and c-3).
-template <typename T, int LIM, typename H, bool RELOAD_B4>
-__device__ __forceinline__ void advect_position(T w0, T bb, T b4_loaded, T k_half, T k_full, AdvectHist<T>& h,
-                                                T& bn, T& emf) {
-  const T w1 = H::prev(w0, h.w1);
-  const T w2 = H::prev(w1, h.w2);
+// flux (end of Sect. 2.4), Eq. (63).  Gives the edge flux at d-face c-3 (the
+// interface between c-4 and c-3) and, for NEED_BN, the new b_t of cell c-4.
+template <typename T, int LIM, typename H, bool NEED_BN, bool RELOAD_B4>
+__device__ __forceinline__ T row_position(T w0, T bb, T b4_loaded, T k_half, T k_full, const RowHist<T>& hi,
+                                          RowHist<T>& ho, T& bn) {
+  const T w1 = H::prev(w0, hi.w1, ho.w1);
+  const T w2 = H::prev(w1, hi.w2, ho.w2);
   const T vbc = T(0.25) * (w2 + T(2) * w1 + w0);   // v-bar of c-1
-  const T b1 = H::prev(bb, h.b1);                   // b of c-1
+  const T b1 = H::prev(bb, hi.b1, ho.b1);                   // b of c-1
   const T fc = vbc * b1;                            // f of c-1
-  const T vb1 = H::prev(vbc, h.vb1);                // v-bar of c-2
+  const T vb1 = H::prev(vbc, hi.vb1, ho.vb1);                // v-bar of c-2
   const T V = T(0.5) * (vb1 + vbc);                 // interface c-3/2
-  const T f2 = H::prev(fc, h.f2);                   // f of c-2
+  const T f2 = H::prev(fc, hi.f2, ho.f2);                   // f of c-2
   const T P1 = V > T(0) ? f2 : fc;                  // Phi1 at c-3/2
-  const T p1 = H::prev(P1, h.p1);                   // Phi1 at c-5/2
-  const T b2 = H::prev(b1, h.b2);                   // b of c-2
+  const T p1 = H::prev(P1, hi.p1, ho.p1);                   // Phi1 at c-5/2
+  const T b2 = H::prev(b1, hi.b2, ho.b2);                   // b of c-2
   const T bp = b2 - k_half * (P1 - p1);             // b' of c-2
   const T fp2 = vb1 * bp;                           // f' of c-2
-  const T vb2 = H::prev(vb1, h.vb2);                // v-bar of c-3
-  const T vb3 = H::prev(vb2, h.vb3);                // v-bar of c-4
+  const T vb2 = H::prev(vb1, hi.vb2, ho.vb2);                // v-bar of c-3
+  const T vb3 = H::prev(vb2, hi.vb3, ho.vb3);                // v-bar of c-4
   const T V7 = T(0.5) * (vb3 + vb2);                // interface c-7/2
-  const T fp3 = H::prev(fp2, h.fp3);
-  const T fp4 = H::prev(fp3, h.fp4);
-  const T fp5 = H::prev(fp4, h.fp5);
-  T P2c;
-  if (V7 > T(0))
-    P2c = fp4 + T(0.5) * limit<T, LIM>(fp4 - fp5, fp3 - fp4);
-  else
-    P2c = fp3 - T(0.5) * limit<T, LIM>(fp3 - fp4, fp2 - fp3);
-  const T P2 = H::prev(P2c, h.P2);                  // Phi2 at c-9/2
-  T b4;
-  if (RELOAD_B4) {
-    b4 = b4_loaded;
-  } else {
-    const T b3 = H::prev(b2, h.b3);
-    b4 = H::prev(b3, h.b4);
+  const T fp3 = H::prev(fp2, hi.fp3, ho.fp3);
+  const T fp4 = H::prev(fp3, hi.fp4, ho.fp4);
+  const T fp5 = H::prev(fp4, hi.fp5, ho.fp5);
+  const T up = fp4 + T(0.5) * limit<T, LIM>(fp4 - fp5, fp3 - fp4);
+  const T dn = fp3 - T(0.5) * limit<T, LIM>(fp3 - fp4, fp2 - fp3);
+  const T P2c = V7 > T(0) ? up : dn;                // Phi2 at c-7/2
+  if (NEED_BN) {
+    const T P2 = H::prev(P2c, hi.P2, ho.P2);                // Phi2 at c-9/2
+    T b4;
+    if (RELOAD_B4) {
+      b4 = b4_loaded;
+    } else {
+      const T b3 = H::prev(b2, hi.b3, ho.b3);
+      b4 = H::prev(b3, hi.b4, ho.b4);
+    }
+    bn = b4 - k_full * (P2c - P2);
   }
-  bn = b4 - k_full * (P2c - P2);
-  emf = P2c;
+  return P2c;
 }
 
+template <typename T>
+struct FieldConsts {
+  T k_half, k_full, dt, ih1, ih2;
+};
+
+template <typename T, int D>
+__device__ __forceinline__ FieldConsts<T> field_consts(const FieldArgs<T>& a) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const double dt = a.sc->dt;
+  FieldConsts<T> k;
+  k.k_half = (T)(dt / (2.0 * a.g.h[D]));
+  k.k_full = (T)(dt / a.g.h[D]);
+  k.dt = (T)dt;
+  k.ih1 = (T)(1.0 / a.g.h[T1]);
+  k.ih2 = (T)(1.0 / a.g.h[T2]);
+  return k;
+}
+
+// Offsets a position needs besides the d offset.  Cells are relative to the
+// thread's own cell (c1, c2) mapped into the box (on the outflow face rows
+// c = n_t the mapped cell is n_t - 1, exactly the ghost the boundary copies);
+// faces are relative to the face-row base (c1, c2).
+struct FieldOffsets {
+  long long c1m, c1p, c2m, c2p;   // cells (c1-1, c2), (c1+1, c2), (c1, c2-1), (c1, c2+1)
+  long long f1p, f2p;             // t1-face c1+1, t2-face c2+1
+};
+
+template <int D>
+__device__ __forceinline__ FieldOffsets field_offsets(const Geo& g, int c1, int c2) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  FieldOffsets o;
+  const int m1 = map_cell(c1, g.n[T1], g.bc[T1]);
+  const int m2 = map_cell(c2, g.n[T2], g.bc[T2]);
+  o.c1m = (long long)(map_cell(c1 - 1, g.n[T1], g.bc[T1]) - m1) * g.st[T1];
+  o.c1p = (long long)(map_cell(c1 + 1, g.n[T1], g.bc[T1]) - m1) * g.st[T1];
+  o.c2m = (long long)(map_cell(c2 - 1, g.n[T2], g.bc[T2]) - m2) * g.st[T2];
+  o.c2p = (long long)(map_cell(c2 + 1, g.n[T2], g.bc[T2]) - m2) * g.st[T2];
+  o.f1p = (long long)(map_face(c1 + 1, g.n[T1], g.bc[T1]) - c1) * g.st[T1];
+  o.f2p = (long long)(map_face(c2 + 1, g.n[T2], g.bc[T2]) - c2) * g.st[T2];
+  return o;
+}
+
+// Byte offsets of everything one position reads, relative to the arrays'
+// base pointers (which carry the d offset when it is wave-uniform).
+struct FieldLane {
+  unsigned cc, c1m, c1p, c2m, c2p;  // cells (c1, c2) and its four transverse neighbours
+  unsigned fA, fB, fC, fD;          // b_t1 at t1-faces c1, c1+1; b_t2 at t2-faces c2, c2+1
+};
+
+template <typename T>
+__device__ __forceinline__ FieldLane field_lane(long long base, long long ownc, const FieldOffsets& o, long long off) {
+  constexpr long long z = sizeof(T);
+  FieldLane l;
+  l.cc = (unsigned)((ownc + off) * z);
+  l.c1m = (unsigned)((ownc + off + o.c1m) * z);
+  l.c1p = (unsigned)((ownc + off + o.c1p) * z);
+  l.c2m = (unsigned)((ownc + off + o.c2m) * z);
+  l.c2p = (unsigned)((ownc + off + o.c2p) * z);
+  l.fA = (unsigned)((base + off) * z);
+  l.fB = (unsigned)((base + off + o.f1p) * z);
+  l.fC = l.fA;
+  l.fD = (unsigned)((base + off + o.f2p) * z);
+  return l;
+}
+
+// Inputs of one position of the four face rows (loads only, so that they can
+// be issued a position ahead of their use).
+template <typename T>
+struct FieldIn {
+  T md[5], rho[5];  // cells (c1, c2), (c1-1, c2), (c1+1, c2), (c1, c2-1), (c1, c2+1)
+  T b[4];           // b_t1 at t1-faces c1, c1+1; b_t2 at t2-faces c2, c2+1
+  T b4a, b4c;       // b_t1, b_t2 of cell c-4 (lanes policy)
+};
+
+template <typename T>
+__device__ __forceinline__ FieldIn<T> field_load(const T* md, const T* rho, const T* bt0, const T* bt1,
+                                                  const FieldLane& l) {
+  FieldIn<T> in;
+  const unsigned c[5] = {l.cc, l.c1m, l.c1p, l.c2m, l.c2p};
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    in.md[i] = ld(md, c[i]);
+    in.rho[i] = ld(rho, c[i]);
+  }
+  in.b[0] = ld(bt0, l.fA);
+  in.b[1] = ld(bt0, l.fB);
+  in.b[2] = ld(bt1, l.fC);
+  in.b[3] = ld(bt1, l.fD);
+  in.b4a = in.b4c = T(0);
+  return in;
+}
+
+// All four face rows at one position.
+template <typename T, int LIM, typename H, bool RELOAD_B4>
+__device__ __forceinline__ void field_compute(const FieldIn<T>& in, const FieldConsts<T>& k, const RowHist<T>* hi,
+                                              RowHist<T>* ho, T& bn1, T& bn2, T& dbd) {
+  // v_d of the five cells around the thread's pencil (Sect. 2.4: the fluid
+  // state current at B_d)
+  T v[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) v[i] = in.md[i] * rcp(in.rho[i]);
+  // Eq. (65) on the four t-faces
+  const T wA = T(0.5) * (v[1] + v[0]), wB = T(0.5) * (v[0] + v[2]);
+  const T wC = T(0.5) * (v[3] + v[0]), wD = T(0.5) * (v[0] + v[4]);
+  T dummy;
+  const T eA = row_position<T, LIM, H, true, RELOAD_B4>(wA, in.b[0], in.b4a, k.k_half, k.k_full, hi[0], ho[0], bn1);
+  const T eB = row_position<T, LIM, H, false, false>(wB, in.b[1], T(0), k.k_half, k.k_full, hi[1], ho[1], dummy);
+  const T eC = row_position<T, LIM, H, true, RELOAD_B4>(wC, in.b[2], in.b4c, k.k_half, k.k_full, hi[2], ho[2], bn2);
+  const T eD = row_position<T, LIM, H, false, false>(wD, in.b[3], T(0), k.k_half, k.k_full, hi[3], ho[3], dummy);
+  // Eq. (64), physical signs: d/dt b_d = d_t1 Phi^t1 + d_t2 Phi^t2
+  dbd = k.dt * ((eB - eA) * k.ih1 + (eD - eC) * k.ih2);
+}
+
+// Strided policy (d = y or z).
 template <typename T, int D, int LIM>
-__global__ __launch_bounds__(256) void advect_strided_kernel(AdvectArgs<T> a) {
+__global__ __launch_bounds__(256) void field_strided_kernel(FieldArgs<T> a) {
   static_assert(D != 0, "x sweeps use the lanes policy");
   constexpr int A = 0;
   constexpr int O = 3 - D;
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   const Geo& g = a.g;
-  const int t = a.t;
   const int nD = g.n[D];
-  const int rA = g.n[A] + ((A == t && g.bc[A] == 1) ? 1 : 0);
-  const int rO = g.n[O] + ((O == t && g.bc[O] == 1) ? 1 : 0);
-  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long total = (long long)rA * rO * a.nseg;
-  if (tid >= total) return;
-  const int ia = (int)(tid % rA);
-  const long long r = tid / rA;
-  const int io = (int)(r % rO);
-  const int sg = (int)(r / rO);
+  const int rA = g.n[A] + g.bc[A];  // outflow adds the face row n
+  const int rO = g.n[O] + g.bc[O];
+  int sg, p;
+  bool active;
+  if (!strided_map(rA * rO, a.nseg, sg, p, active)) return;
   const int s0 = sg * a.seg;
   const int s1 = min(nD, s0 + a.seg);
   const bool last = (s1 == nD);
   const bool outD = g.bc[D] == 1;
   int c[3];
-  c[A] = ia;
-  c[O] = io;
+  c[A] = p % rA;
+  c[O] = p / rA;
   c[D] = 0;
+  const int c1 = c[T1], c2 = c[T2];
+  const bool own1 = active && c2 < g.n[T2];   // b_t1 row is real
+  const bool own2 = active && c1 < g.n[T1];   // b_t2 row is real
+  const bool ownd = own1 && own2;             // b_d row is real
   const long long stD = g.st[D];
-  const long long base = (long long)c[A] * g.st[A] + (long long)c[O] * g.st[O];
-  const int ft = c[t];
-  const long long cell_lo = base + (long long)(map_cell(ft - 1, g.n[t], g.bc[t]) - ft) * g.st[t];
-  const long long cell_hi = base + (long long)(map_cell(ft, g.n[t], g.bc[t]) - ft) * g.st[t];
-  const double dt = a.sc->dt;
-  const T k_half = (T)(dt / (2.0 * g.h[D]));
-  const T k_full = (T)(dt / g.h[D]);
-  AdvectHist<T> h;
-  h.zero();
-  const int npos = (s1 - s0) + 8;
-#pragma unroll 2
-  for (int it = 0; it < npos; ++it) {
-    const int s = s0 - 4 + it;
+  const long long base = (long long)c1 * g.st[T1] + (long long)c2 * g.st[T2];
+  const long long ownc = (long long)map_cell(c1, g.n[T1], g.bc[T1]) * g.st[T1] +
+                         (long long)map_cell(c2, g.n[T2], g.bc[T2]) * g.st[T2];
+  const FieldOffsets oc = field_offsets<D>(g, c1, c2);
+  const FieldConsts<T> k = field_consts<T, D>(a);
+  RowHist<T> hA[4], hB[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    hA[q].zero();
+    hB[q].zero();
+  }
+  const FieldLane l = field_lane<T>(base, ownc, oc, 0);  // lane byte offsets, fixed along the pencil
+  auto load = [&](int it) {
+    const int s = s0 - 4 + it;  // uniform
     const long long off = (long long)map_cell(s, nD, g.bc[D]) * stD;
-    const T vlo = a.md[cell_lo + off] * rcp(a.rho[cell_lo + off]);
-    const T vhi = a.md[cell_hi + off] * rcp(a.rho[cell_hi + off]);
-    const T w0 = T(0.5) * (vlo + vhi);
-    const T bb = a.bt[base + off];
-    T bn, e;
-    advect_position<T, LIM, StridedHist, false>(w0, bb, T(0), k_half, k_full, h, bn, e);
-    if (it >= 8) a.bto[base + (long long)(s - 4) * stD] = bn;
+    return field_load<T>(a.md + off, a.rho + off, a.bt[0] + off, a.bt[1] + off, l);
+  };
+  auto compute = [&](int it, const FieldIn<T>& in, const RowHist<T>* hi, RowHist<T>* ho) {
+    const int s = s0 - 4 + it;
+    T bn1, bn2, dbd;
+    field_compute<T, LIM, StridedHist, false>(in, k, hi, ho, bn1, bn2, dbd);
+    if (it >= 8 && s - 4 < s1) {
+      const long long ob = (long long)(s - 4) * stD;
+      if (own1) st(a.bto[0] + ob, l.fA, bn1);
+      if (own2) st(a.bto[1] + ob, l.fA, bn2);
+    }
     const int fd = s - 3;
-    if (it >= 7 && (fd < s1 || (last && outD && fd == nD))) a.emf[base + (long long)fd * stD] = e;
+    if (ownd && it >= 7 && (fd < s1 || (last && outD && fd == nD))) {
+      const long long of = (long long)fd * stD;
+      st(a.bdo + of, l.fA, ld(a.bd + of, l.fA) + dbd);
+    }
+  };
+  // positions s0-4 .. s1+3, padded to an even count (the pad writes nothing).
+  // No lookahead here: the extra registers cost more occupancy than the
+  // prefetch hides (measured).
+  const int npos = (s1 - s0) + 8;
+  for (int it = 0; it < npos; it += 2) {
+    compute(it, load(it), hA, hB);
+    compute(it + 1, load(it + 1), hB, hA);
   }
 }
 
-// Lanes policy for B_x: each wave streams whole face rows along x, each row
-// padded by 4 positions before and 4 after.
+// Lanes policy (d = x): waves stream whole rows (y, z) of faces, each padded
+// by 4 positions before and 4 after.
 template <typename T, int LIM>
-__global__ __launch_bounds__(256) void advect_lanes_kernel(AdvectArgs<T> a) {
+__global__ __launch_bounds__(256) void field_lanes_kernel(FieldArgs<T> a) {
+  constexpr int D = 0;
   const Geo& g = a.g;
-  const int t = a.t;  // 1 or 2
   const int nx = g.n[0];
   const bool outx = g.bc[0] == 1;
   const int L = nx + 8;
-  const int ry = g.n[1] + ((t == 1 && g.bc[1] == 1) ? 1 : 0);
-  const int rz = g.n[2] + ((t == 2 && g.bc[2] == 1) ? 1 : 0);
+  const int ry = g.n[1] + g.bc[1];
+  const int rz = g.n[2] + g.bc[2];
   const long long nrows = (long long)ry * rz;
   const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   const long long r0 = wave * a.rows_per_wave;
-  if (r0 >= nrows) return;
+  if (r0 >= nrows) return;  // whole wave exits together
   const int rows = (int)min((long long)a.rows_per_wave, nrows - r0);
   const int npos = rows * L;
   const int nit = (npos + 63) >> 6;
-  const double dt = a.sc->dt;
-  const T k_half = (T)(dt / (2.0 * g.h[0]));
-  const T k_full = (T)(dt / g.h[0]);
-  AdvectHist<T> h;
-  h.zero();
-  for (int it = 0; it < nit; ++it) {
-    const int q = (it << 6) + lane;
-    const bool valid = q < npos;
-    const int qq = valid ? q : npos - 1;
-    const int rr = qq / L;
-    const int cpos = qq - rr * L - 4;  // cell index along x (-4 .. nx+3)
-    const long long row = r0 + rr;
-    const int y = (int)(row % ry), z = (int)(row / ry);
-    const long long base = (long long)y * g.st[1] + (long long)z * g.st[2];
-    const int ft = (t == 1) ? y : z;
-    const long long st_t = g.st[t];
-    const long long cell_lo = base + (long long)(map_cell(ft - 1, g.n[t], g.bc[t]) - ft) * st_t;
-    const long long cell_hi = base + (long long)(map_cell(ft, g.n[t], g.bc[t]) - ft) * st_t;
-    const int ms = map_cell(cpos, nx, g.bc[0]);
-    const T vlo = a.md[cell_lo + ms] * rcp(a.rho[cell_lo + ms]);
-    const T vhi = a.md[cell_hi + ms] * rcp(a.rho[cell_hi + ms]);
-    const T w0 = T(0.5) * (vlo + vhi);
-    const T bb = a.bt[base + ms];
-    const T b4 = a.bt[base + map_cell(cpos - 4, nx, g.bc[0])];
-    T bn, e;
-    advect_position<T, LIM, LaneHist, true>(w0, bb, b4, k_half, k_full, h, bn, e);
-    const int cb = cpos - 4;
-    if (valid && cb >= 0 && cb < nx) a.bto[base + cb] = bn;
-    const int fd = cpos - 3;
-    if (valid && fd >= 0 && (fd < nx || (outx && fd == nx))) a.emf[base + fd] = e;
+  const FieldConsts<T> k = field_consts<T, D>(a);
+  RowHist<T> hA[4], hB[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    hA[q].zero();
+    hB[q].zero();
   }
-}
-
-// ------------------------------------------------------------ B_d, constraint
-template <typename T>
-struct ConstraintArgs {
-  const T* bd;
-  T* bdo;
-  const T* e1;  // EMF of b_t1
-  const T* e2;  // EMF of b_t2
-  Geo g;
-  const Scalars* sc;
-};
-
-// Eq. (64) with the physical signs: b_d += dt (d_t1 Phi^t1 + d_t2 Phi^t2).
-template <typename T, int D>
-__global__ __launch_bounds__(256) void field_constraint_kernel(ConstraintArgs<T> a) {
-  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  const Geo& g = a.g;
-  const int nfx = g.n[0] + ((D == 0 && g.bc[0] == 1) ? 1 : 0);
-  const int nfy = g.n[1] + ((D == 1 && g.bc[1] == 1) ? 1 : 0);
-  const int nfz = g.n[2] + ((D == 2 && g.bc[2] == 1) ? 1 : 0);
-  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long total = (long long)nfx * nfy * nfz;
-  if (tid >= total) return;
-  int c[3];
-  c[0] = (int)(tid % nfx);
-  const long long r = tid / nfx;
-  c[1] = (int)(r % nfy);
-  c[2] = (int)(r / nfy);
-  const long long idx = (long long)c[0] * g.st[0] + (long long)c[1] * g.st[1] + (long long)c[2] * g.st[2];
-  const long long up1 = idx + (long long)(map_face(c[T1] + 1, g.n[T1], g.bc[T1]) - c[T1]) * g.st[T1];
-  const long long up2 = idx + (long long)(map_face(c[T2] + 1, g.n[T2], g.bc[T2]) - c[T2]) * g.st[T2];
-  const double dt = a.sc->dt;
-  const T dtT = (T)dt;
-  const T ih1 = (T)(1.0 / g.h[T1]), ih2 = (T)(1.0 / g.h[T2]);
-  a.bdo[idx] = a.bd[idx] + dtT * ((a.e1[up1] - a.e1[idx]) * ih1 + (a.e2[up2] - a.e2[idx]) * ih2);
+  RowCursor rc;
+  rc.init(lane, L, r0, rows, ry);
+  long long base = 0, ownc = 0;
+  FieldOffsets o;
+  bool own1 = false, own2 = false;
+  struct In {
+    FieldIn<T> f;
+    unsigned b4off, fo;  // byte offsets of cell c-4 and d-face c-3 in the row
+    int cpos;
+    bool valid, own1, own2;
+  };
+  auto load = [&](int it) {
+    if (rc.moved) {
+      const int c1 = rc.y, c2 = rc.z;  // y, z face rows
+      base = (long long)c1 * g.st[1] + (long long)c2 * g.st[2];
+      ownc = (long long)map_cell_near(c1, g.n[1], g.bc[1]) * g.st[1] +
+             (long long)map_cell_near(c2, g.n[2], g.bc[2]) * g.st[2];
+      o = field_offsets<D>(g, c1, c2);
+      own1 = c2 < g.n[2];
+      own2 = c1 < g.n[1];
+    }
+    In in;
+    in.valid = (it << 6) + lane < npos;
+    in.cpos = rc.cp - 4;  // cell index along x (-4 .. nx+3)
+    in.own1 = own1;
+    in.own2 = own2;
+    const int mx = map_cell_near(in.cpos, nx, g.bc[0]);
+    const int m4 = map_cell_near(in.cpos - 4, nx, g.bc[0]);
+    const FieldLane l = field_lane<T>(base, ownc, o, mx);
+    in.f = field_load<T>(a.md, a.rho, a.bt[0], a.bt[1], l);
+    in.b4off = (unsigned)((base + m4) * (long long)sizeof(T));
+    in.f.b4a = ld(a.bt[0], in.b4off);
+    in.f.b4c = ld(a.bt[1], in.b4off);
+    in.fo = (unsigned)((base + max(in.cpos - 3, 0)) * (long long)sizeof(T));
+    rc.advance(L, rows, ry);
+    return in;
+  };
+  auto compute = [&](const In& in, const RowHist<T>* hi, RowHist<T>* ho) {
+    T bn1, bn2, dbd;
+    field_compute<T, LIM, LaneHist, true>(in.f, k, hi, ho, bn1, bn2, dbd);
+    const int cb = in.cpos - 4;
+    if (in.valid && cb >= 0 && cb < nx) {
+      if (in.own1) st(a.bto[0], in.b4off, bn1);
+      if (in.own2) st(a.bto[1], in.b4off, bn2);
+    }
+    const int fd = in.cpos - 3;
+    if (in.valid && in.own1 && in.own2 && fd >= 0 && (fd < nx || (outx && fd == nx)))
+      st(a.bdo, in.fo, ld(a.bd, in.fo) + dbd);
+  };
+  In cur = load(0);
+  for (int it = 0; it < nit; it += 2) {
+    const In nxt = load(it + 1);
+    compute(cur, hA, hB);
+    cur = load(it + 2);
+    compute(nxt, hB, hA);
+  }
 }
 
 // ------------------------------------------------------------ CFL + state check

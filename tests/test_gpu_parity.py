@@ -287,3 +287,22 @@ def test_gpu_rejects_bad_state():
     with pytest.raises(fish.FishError) as e:
         g.set_state(st)
     assert e.value.code == fish.FISH_ERR_STATE
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-6)])
+def test_fused_cfl_matches_standalone_reduction(prec, tol):
+    """The last x sweep of a step reduces the next CFL step; it must agree with
+    the standalone reduction of the same state (and with the oracle)."""
+    print(f"fused CFL {prec} 24x20x16", flush=True)
+    n = (24, 20, 16)
+    st = fi.random_fourier_state(n, seed=21, mach=0.7, beta=2.0, kmax=3)
+    g = _box(n, precision=prec)
+    g.set_state(st)
+    g.strang_step(0.0)
+    fused = g.cfl_dt()
+    out = g.get_state()          # runs the standalone check/reduction
+    standalone = g.cfl_dt()
+    assert abs(fused - standalone) <= tol * standalone
+    o = Oracle(*n)
+    o.set_state(out)
+    assert abs(o.cfl_dt() - standalone) <= max(tol, 1e-14) * standalone
