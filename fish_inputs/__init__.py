@@ -86,13 +86,15 @@ def _modes(coords, ks, thetas, amps):
     Uses separable complex exponentials (exact up to round-off).
     """
     x, y, z = coords
-    out = np.zeros((len(z), len(y), len(x)))
-    for k, th, a in zip(ks, thetas, amps):
-        ex = np.exp(2j * np.pi * k[0] * x)
-        ey = np.exp(2j * np.pi * k[1] * y)
-        ez = np.exp(2j * np.pi * k[2] * z) * (a * np.exp(1j * th))
-        out += (ez[:, None, None] * ey[None, :, None] * ex[None, None, :]).real
-    return out
+    ks = np.asarray(ks, dtype=np.float64)
+    ph = np.asarray(amps, dtype=np.float64) * np.exp(1j * np.asarray(thetas, dtype=np.float64))
+    ex = np.exp(2j * np.pi * np.outer(ks[:, 0], x))                      # (m, nx)
+    ey = np.exp(2j * np.pi * np.outer(ks[:, 1], y))                      # (m, ny)
+    ez = np.exp(2j * np.pi * np.outer(ks[:, 2], z)) * ph[:, None]        # (m, nz)
+    t = (ez[:, :, None] * ey[:, None, :]).reshape(len(ks), -1)           # (m, nz*ny)
+    # real part of the sum over modes as two real products over the mode index
+    out = t.real.T @ ex.real - t.imag.T @ ex.imag
+    return out.reshape(len(z), len(y), len(x))
 
 
 def curl_of_potential(Ax, Ay, Az, dx, dy, dz):

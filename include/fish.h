@@ -148,12 +148,171 @@ enum {
 int fish_timing_enable(fish_ctx* ctx, int mask, int max_launches);
 int fish_timing_read(fish_ctx* ctx, int* launches, double* total_ms);
 
+/* Kernel kinds of the sweeps, for the autotuner: the fluid sweeps along x, y,
+ * z, the field sweeps along x, y, z, and the CFL check. */
+enum {
+  FISH_KIND_FLUID_X = 0, FISH_KIND_FLUID_Y, FISH_KIND_FLUID_Z,
+  FISH_KIND_FIELD_X, FISH_KIND_FIELD_Y, FISH_KIND_FIELD_Z,
+  FISH_KIND_CHECK, FISH_NUM_KINDS
+};
+
+/* Autotuner (not part of the scheme): times every candidate work shape of
+ * each sweep kind on the current state, reps launches each, and keeps the
+ * fastest; the state is unchanged.  Shapes: stream positions per wavefront
+ * for the x kinds (whole rows), segment length along the sweep for the y/z
+ * kinds.  targets_out (may be NULL) receives FISH_NUM_KINDS chosen values.
+ * Results do not depend on the shapes (each cell is computed by the same
+ * operations whatever wave computes it).  Synchronises the stream. */
+int fish_autotune(fish_ctx* ctx, int reps, int32_t* targets_out);
+
 /* Self-test of the wavefront lane-shift primitive the x sweeps stream with
  * (no context): one wave of 64 lanes runs two iterations with lane values
  * v = 100*it + lane; out128[64*it + lane] receives the value one stream
  * position back (lane-1 of the same iteration, lane 63 of the previous one
  * for lane 0; -1 before the first).  Synchronous; the caller owns out128. */
 int fish_selftest_lane_shift(int device, float* out128);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent boxes of different shapes advanced together.
+ *
+ * A batch owns one device pool per field (two buffers each, plus phi with
+ * gravity) of pool_bytes in total and places each box at an offset of the
+ * pools (first fit; a removed box's range is returned and merged).  Every
+ * launch of a step covers all boxes of the batch: a device table lists the
+ * boxes and, per kernel kind, the box of every wavefront.  Each box takes its
+ * own CFL step (Eq. 14) every double step; boxes never interact, so a box's
+ * result is the same alone or in any mix (bitwise, same precision).
+ * The scheme settings (gamma, limiter, predictor alpha, precision, gravity,
+ * HSE) are per batch; the geometry and Courant number per box.
+ * ------------------------------------------------------------------------ */
+typedef struct fish_batch fish_batch;
+
+typedef struct fish_batch_params {
+  double gamma;
+  int32_t limiter;
+  double predictor_alpha;
+  int32_t precision;
+  int32_t gravity;
+  int32_t hse;
+  int32_t device;
+  void* stream;              /* NULL: the batch creates its own (graphs cannot
+                                capture the null stream)                   */
+  size_t pool_bytes;         /* device bytes for box state (see fish_box_pool_bytes) */
+  int32_t max_boxes;         /* box slots, >= 1                             */
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, size_t bytes, void* stream, void* user);
+  void* alloc_user;
+} fish_batch_params;
+
+typedef struct fish_box {
+  int32_t nx, ny, nz;        /* interior cells per axis, >= 1              */
+  double dx, dy, dz;         /* spacing > 0                                 */
+  double cfl;                /* Courant number, 0 < k <= 1                  */
+  int32_t bc[3];             /* FISH_PERIODIC / FISH_OUTFLOW per axis       */
+} fish_box;
+
+/* Pool bytes one box takes in a batch of the given precision and gravity
+ * (its arrays, both buffers, padded to 64 elements): the admission test of a
+ * caller that budgets device memory.  0 for NULL. */
+size_t fish_box_pool_bytes(const fish_box* box, int precision, int gravity);
+
+/* Create / destroy a batch (fish_params conventions: FISH_ERR_ARG on a bad
+ * field, FISH_ERR_NOMEM when the pools cannot be allocated). */
+int fish_batch_create(const fish_batch_params* p, fish_batch** out);
+void fish_batch_destroy(fish_batch* b);
+const char* fish_batch_last_error(const fish_batch* b);
+size_t fish_batch_device_bytes(const fish_batch* b);
+/* Pool bytes not held by any box (possibly fragmented). */
+size_t fish_batch_free_bytes(const fish_batch* b);
+/* Boxes in the batch. */
+int fish_batch_count(const fish_batch* b);
+
+/* Add a box with its state (layouts of fish_set_state).  *id_out receives
+ * its id (>= 0).  FISH_ERR_NOMEM when no slot or pool range is free (the
+ * batch is unchanged), FISH_ERR_STATE when the state fails the check (the box
+ * is not added).  Synchronises the stream. */
+int fish_batch_add(fish_batch* b, const fish_box* box, const double* cell5, const double* bx,
+                   const double* by, const double* bz, const double* phi, int* id_out);
+
+/* Remove a box and return its pool range.  Synchronises the stream. */
+int fish_batch_remove(fish_batch* b, int id);
+
+/* Download one box's state and time (fish_get_state layouts; NULL skips an
+ * array).  FISH_ERR_STATE if the box's sticky state flag is set (a box with a
+ * bad state stops: its later steps have dt = 0).  Synchronises the stream. */
+int fish_batch_get(fish_batch* b, int id, double* cell5, double* bx, double* by, double* bz,
+                   double* t_out);
+
+/* Time, last dt and the sticky state flag of one box.  Synchronises. */
+int fish_batch_box_info(fish_batch* b, int id, double* t_out, double* dt_out, int* bad_out);
+
+/* nsteps double steps of every box, each with its own CFL step.
+ * Asynchronous. */
+int fish_batch_step(fish_batch* b, int nsteps);
+
+/* With on != 0 the launches of one double step are captured once into a HIP
+ * graph (per set of boxes) and replayed by fish_batch_step. */
+int fish_batch_use_graph(fish_batch* b, int on);
+
+/* The autotuner of fish_autotune over all boxes of the batch. */
+int fish_batch_autotune(fish_batch* b, int reps, int32_t* targets_out);
+
+/* Wait for the batch's stream. */
+int fish_batch_sync(fish_batch* b);
+
+/* The measurement hook of fish_timing_enable / fish_timing_read (eager
+ * launches only: fish_batch_step does not replay a graph while it is on). */
+int fish_batch_timing_enable(fish_batch* b, int mask, int max_launches);
+int fish_batch_timing_read(fish_batch* b, int* launches, double* total_ms);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over a batch.
+ *
+ * Requests (a box, its state and a number of double steps) wait in a FIFO
+ * queue.  Each fish_server_pump call
+ *   1. admits queued requests in arrival order while the head fits in the
+ *      batch's pool (the HBM budget; a request never overtakes the head),
+ *   2. advances every resident box by k = min(chunk, fewest steps left) double
+ *      steps in the same launches (each box with its own CFL step), and
+ *   3. retires the boxes that are done: their state is written to the
+ *      request's output arrays and their pool range is freed.
+ * A request's result is the same as stepping its box alone (bitwise).
+ * ------------------------------------------------------------------------ */
+typedef struct fish_server fish_server;
+
+typedef struct fish_request {
+  fish_box box;
+  int32_t nsteps;                    /* double steps, >= 1                          */
+  const double *cell5, *bx, *by, *bz, *phi;  /* input state (fish_set_state layouts),
+                                        read at admission; phi only with gravity */
+  double *out_cell5, *out_bx, *out_by, *out_bz;  /* final state, written at
+                                        retirement (any may be NULL)             */
+  int64_t tag;                       /* returned by fish_server_pump on completion  */
+} fish_request;
+
+/* Create a server whose batch has the given parameters; chunk_steps >= 1 is
+ * the most steps advanced between admissions. */
+int fish_server_create(const fish_batch_params* p, int chunk_steps, fish_server** out);
+void fish_server_destroy(fish_server* s);
+const char* fish_server_last_error(const fish_server* s);
+/* The server's batch (owned by the server; for autotuning or graphs). */
+fish_batch* fish_server_batch(fish_server* s);
+
+/* Queue a request.  The request record is copied; its arrays are owned by the
+ * caller and must stay valid until the request completes.  FISH_ERR_NOMEM if
+ * the box can never fit the pool. */
+int fish_server_submit(fish_server* s, const fish_request* r);
+
+/* One scheduling round (above).  Completed requests: *ndone tags in
+ * done_tags[0..max_done) with their status in done_status (FISH_OK, or
+ * FISH_ERR_STATE when the box's state went bad; may be NULL).  Synchronises
+ * the stream. */
+int fish_server_pump(fish_server* s, int64_t* done_tags, int32_t* done_status, int max_done, int* ndone);
+
+/* Queue length, resident boxes, free pool bytes and cells x double steps
+ * advanced so far (any pointer may be NULL). */
+int fish_server_stats(const fish_server* s, int* queued, int* resident, size_t* pool_free,
+                      int64_t* cell_steps);
 
 #ifdef __cplusplus
 }

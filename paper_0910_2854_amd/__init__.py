@@ -52,10 +52,55 @@ class FishError(RuntimeError):
         self.code = code
 
 
+class BatchParams(ctypes.Structure):
+    _fields_ = [
+        ("gamma", ctypes.c_double),
+        ("limiter", ctypes.c_int32),
+        ("predictor_alpha", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("gravity", ctypes.c_int32), ("hse", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+        ("pool_bytes", ctypes.c_size_t),
+        ("max_boxes", ctypes.c_int32),
+        ("alloc", _ALLOC), ("free", _FREE),
+        ("alloc_user", ctypes.c_void_p),
+    ]
+
+
+class BoxGeom(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("bc", ctypes.c_int32 * 3),
+    ]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("box", BoxGeom),
+        ("nsteps", ctypes.c_int32),
+        ("cell5", ctypes.POINTER(ctypes.c_double)), ("bx", ctypes.POINTER(ctypes.c_double)),
+        ("by", ctypes.POINTER(ctypes.c_double)), ("bz", ctypes.POINTER(ctypes.c_double)),
+        ("phi", ctypes.POINTER(ctypes.c_double)),
+        ("out_cell5", ctypes.POINTER(ctypes.c_double)), ("out_bx", ctypes.POINTER(ctypes.c_double)),
+        ("out_by", ctypes.POINTER(ctypes.c_double)), ("out_bz", ctypes.POINTER(ctypes.c_double)),
+        ("tag", ctypes.c_int64),
+    ]
+
+
 EXPORTS = ("fish_create", "fish_destroy", "fish_last_error", "fish_set_state", "fish_get_state",
            "fish_cfl_dt", "fish_strang_step", "fish_sweep", "fish_diagnostics", "fish_device_bytes",
-           "fish_timing_enable", "fish_timing_read", "fish_selftest_lane_shift")
+           "fish_timing_enable", "fish_timing_read", "fish_selftest_lane_shift", "fish_autotune",
+           "fish_box_pool_bytes", "fish_batch_create", "fish_batch_destroy", "fish_batch_last_error",
+           "fish_batch_device_bytes", "fish_batch_free_bytes", "fish_batch_count", "fish_batch_add",
+           "fish_batch_remove", "fish_batch_get", "fish_batch_box_info", "fish_batch_step",
+           "fish_batch_use_graph", "fish_batch_autotune", "fish_batch_sync", "fish_batch_timing_enable",
+           "fish_batch_timing_read", "fish_server_create", "fish_server_destroy", "fish_server_last_error",
+           "fish_server_batch", "fish_server_submit", "fish_server_pump", "fish_server_stats")
 KERNEL_FLUID, KERNEL_FIELD, KERNEL_CHECK = 1, 2, 8
+KINDS = ("fluid_x", "fluid_y", "fluid_z", "field_x", "field_y", "field_z", "check")
 
 _lib = None
 
@@ -86,8 +131,47 @@ def load_library(path: str = LIB_PATH):
     lib.fish_timing_read.argtypes = [vp, P(ctypes.c_int), P(d)]
     lib.fish_selftest_lane_shift.argtypes = [ctypes.c_int, P(ctypes.c_float)]
     lib.fish_selftest_lane_shift.restype = ctypes.c_int
+    i32p = P(ctypes.c_int32)
+    lib.fish_autotune.argtypes = [vp, ctypes.c_int, i32p]
+    lib.fish_box_pool_bytes.argtypes = [P(BoxGeom), ctypes.c_int, ctypes.c_int]
+    lib.fish_box_pool_bytes.restype = ctypes.c_size_t
+    lib.fish_batch_create.argtypes = [P(BatchParams), P(vp)]
+    lib.fish_batch_destroy.argtypes = [vp]
+    lib.fish_batch_destroy.restype = None
+    lib.fish_batch_last_error.argtypes = [vp]
+    lib.fish_batch_last_error.restype = ctypes.c_char_p
+    lib.fish_batch_device_bytes.argtypes = [vp]
+    lib.fish_batch_device_bytes.restype = ctypes.c_size_t
+    lib.fish_batch_free_bytes.argtypes = [vp]
+    lib.fish_batch_free_bytes.restype = ctypes.c_size_t
+    lib.fish_batch_count.argtypes = [vp]
+    lib.fish_batch_add.argtypes = [vp, P(BoxGeom), P(d), P(d), P(d), P(d), P(d), P(ctypes.c_int)]
+    lib.fish_batch_remove.argtypes = [vp, ctypes.c_int]
+    lib.fish_batch_get.argtypes = [vp, ctypes.c_int, P(d), P(d), P(d), P(d), P(d)]
+    lib.fish_batch_box_info.argtypes = [vp, ctypes.c_int, P(d), P(d), P(ctypes.c_int)]
+    lib.fish_batch_step.argtypes = [vp, ctypes.c_int]
+    lib.fish_batch_use_graph.argtypes = [vp, ctypes.c_int]
+    lib.fish_batch_autotune.argtypes = [vp, ctypes.c_int, i32p]
+    lib.fish_batch_sync.argtypes = [vp]
+    lib.fish_batch_timing_enable.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    lib.fish_batch_timing_read.argtypes = [vp, P(ctypes.c_int), P(d)]
+    lib.fish_server_create.argtypes = [P(BatchParams), ctypes.c_int, P(vp)]
+    lib.fish_server_destroy.argtypes = [vp]
+    lib.fish_server_destroy.restype = None
+    lib.fish_server_last_error.argtypes = [vp]
+    lib.fish_server_last_error.restype = ctypes.c_char_p
+    lib.fish_server_batch.argtypes = [vp]
+    lib.fish_server_batch.restype = vp
+    lib.fish_server_submit.argtypes = [vp, P(Request)]
+    lib.fish_server_pump.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int32), ctypes.c_int, P(ctypes.c_int)]
+    lib.fish_server_stats.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_size_t), P(ctypes.c_int64)]
+    for name in ("fish_server_create", "fish_server_submit", "fish_server_pump", "fish_server_stats"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("fish_create", "fish_set_state", "fish_get_state", "fish_cfl_dt", "fish_strang_step",
-                 "fish_sweep", "fish_diagnostics", "fish_timing_enable", "fish_timing_read"):
+                 "fish_sweep", "fish_diagnostics", "fish_timing_enable", "fish_timing_read", "fish_autotune",
+                 "fish_batch_create", "fish_batch_count", "fish_batch_add", "fish_batch_remove", "fish_batch_get",
+                 "fish_batch_box_info", "fish_batch_step", "fish_batch_use_graph", "fish_batch_autotune",
+                 "fish_batch_sync", "fish_batch_timing_enable", "fish_batch_timing_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -243,5 +327,258 @@ class Box:
     def diagnostics(self):
         out = np.zeros(10)
         self._check(self._lib.fish_diagnostics(self._h, _dptr(out)))
-        return {"mass": out[0], "mom": out[1:4].copy(), "energy": out[4], "flux": out[5:8].copy(),
-                "divb_max": out[8], "bmax": out[9]}
+        return _diag_dict(out)
+
+    def autotune(self, reps=3):
+        """Pick the fastest work shape of every sweep kind; returns {kind: target}."""
+        t = (ctypes.c_int32 * 7)()
+        self._check(self._lib.fish_autotune(self._h, int(reps), t))
+        return dict(zip(KINDS, list(t)))
+
+
+def _diag_dict(out):
+    return {"mass": out[0], "mom": out[1:4].copy(), "energy": out[4], "flux": out[5:8].copy(),
+            "divb_max": out[8], "bmax": out[9]}
+
+
+def _geom(n, h=None, cfl=0.5, bc=(PERIODIC,) * 3):
+    nx, ny, nz = (int(v) for v in n)
+    g = BoxGeom()
+    g.nx, g.ny, g.nz = nx, ny, nz
+    if h is None:
+        h = (1.0 / nx, 1.0 / ny, 1.0 / nz)
+    g.dx, g.dy, g.dz = (float(v) for v in h)
+    g.cfl = float(cfl)
+    for a in range(3):
+        g.bc[a] = int(bc[a])
+    return g
+
+
+def box_pool_bytes(n, precision="fp32", gravity=False, bc=(PERIODIC,) * 3):
+    """Device bytes one box (nx, ny, nz) takes in a batch."""
+    lib = load_library()
+    prec = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
+    return int(lib.fish_box_pool_bytes(ctypes.byref(_geom(n, bc=bc)), prec, int(bool(gravity))))
+
+
+def _batch_params(owner, pool_bytes, max_boxes, gamma, limiter, predictor_alpha, precision, gravity, hse, device,
+                  stream, use_torch_allocator):
+    p = BatchParams()
+    p.gamma = float(gamma)
+    p.limiter = int(limiter)
+    p.predictor_alpha = float(predictor_alpha)
+    p.precision = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
+    p.gravity, p.hse = int(bool(gravity)), int(bool(hse))
+    p.device = int(device)
+    p.pool_bytes = int(pool_bytes)
+    p.max_boxes = int(max_boxes)
+    owner._allocator = None
+    if use_torch_allocator or stream is None:
+        import torch
+        torch.cuda.set_device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        if use_torch_allocator:
+            owner._allocator = _TorchAllocator(device)
+            p.alloc, p.free = owner._allocator.alloc, owner._allocator.free
+    p.stream = ctypes.c_void_p(int(stream)) if stream else None
+    return p
+
+
+class Batch:
+    """Many independent boxes advanced together (one launch per sub-operator
+    covers them all), each with its own CFL step."""
+
+    def __init__(self, pool_bytes, max_boxes=4096, gamma=5.0 / 3.0, limiter=VANLEER, predictor_alpha=1.0,
+                 precision="fp32", gravity=False, hse=False, device=0, stream=None, use_torch_allocator=True):
+        lib = load_library()
+        self._lib = lib
+        p = _batch_params(self, pool_bytes, max_boxes, gamma, limiter, predictor_alpha, precision, gravity, hse,
+                          device, stream, use_torch_allocator)
+        self.params = p
+        self.gravity = bool(gravity)
+        self.shapes = {}
+        h = ctypes.c_void_p()
+        rc = lib.fish_batch_create(ctypes.byref(p), ctypes.byref(h))
+        if rc != FISH_OK:
+            raise FishError(rc, "fish_batch_create failed")
+        self._h = h
+
+    def _check(self, rc):
+        if rc != FISH_OK:
+            raise FishError(rc, self._lib.fish_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.fish_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def device_bytes(self):
+        return int(self._lib.fish_batch_device_bytes(self._h))
+
+    @property
+    def free_bytes(self):
+        return int(self._lib.fish_batch_free_bytes(self._h))
+
+    def __len__(self):
+        return int(self._lib.fish_batch_count(self._h))
+
+    def add(self, st, h=None, cfl=0.5, bc=(PERIODIC,) * 3):
+        """Add a box with state dict st (layouts of Box.set_state); returns its id."""
+        cell = np.ascontiguousarray(st["cell"], dtype=np.float64)
+        _, nz, ny, nx = cell.shape
+        bx = np.ascontiguousarray(st["bx"], dtype=np.float64)
+        by = np.ascontiguousarray(st["by"], dtype=np.float64)
+        bz = np.ascontiguousarray(st["bz"], dtype=np.float64)
+        if bx.shape != (nz, ny, nx + 1) or by.shape != (nz, ny + 1, nx) or bz.shape != (nz + 1, ny, nx):
+            raise ValueError("face arrays do not match the cell array")
+        phi = st.get("phi") if self.gravity else None
+        if phi is not None:
+            phi = np.ascontiguousarray(phi, dtype=np.float64)
+        g = _geom((nx, ny, nz), h, cfl, bc)
+        i = ctypes.c_int(-1)
+        self._check(self._lib.fish_batch_add(self._h, ctypes.byref(g), _dptr(cell), _dptr(bx), _dptr(by), _dptr(bz),
+                                             _dptr(phi), ctypes.byref(i)))
+        self.shapes[i.value] = (nz, ny, nx)
+        return i.value
+
+    def remove(self, box_id):
+        self._check(self._lib.fish_batch_remove(self._h, int(box_id)))
+        self.shapes.pop(box_id, None)
+
+    def get(self, box_id, check=True):
+        nz, ny, nx = self.shapes[box_id]
+        cell = np.empty((5, nz, ny, nx))
+        bx = np.empty((nz, ny, nx + 1))
+        by = np.empty((nz, ny + 1, nx))
+        bz = np.empty((nz + 1, ny, nx))
+        t = ctypes.c_double()
+        rc = self._lib.fish_batch_get(self._h, int(box_id), _dptr(cell), _dptr(bx), _dptr(by), _dptr(bz),
+                                      ctypes.byref(t))
+        if check:
+            self._check(rc)
+        return {"cell": cell, "bx": bx, "by": by, "bz": bz, "t": t.value, "status": rc}
+
+    def info(self, box_id):
+        t, dt, bad = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        self._check(self._lib.fish_batch_box_info(self._h, int(box_id), ctypes.byref(t), ctypes.byref(dt),
+                                                  ctypes.byref(bad)))
+        return {"t": t.value, "dt": dt.value, "bad": bool(bad.value)}
+
+    def step(self, nsteps=1):
+        self._check(self._lib.fish_batch_step(self._h, int(nsteps)))
+
+    def use_graph(self, on=True):
+        self._check(self._lib.fish_batch_use_graph(self._h, int(bool(on))))
+
+    def autotune(self, reps=3):
+        t = (ctypes.c_int32 * 7)()
+        self._check(self._lib.fish_batch_autotune(self._h, int(reps), t))
+        return dict(zip(KINDS, list(t)))
+
+    def sync(self):
+        self._check(self._lib.fish_batch_sync(self._h))
+
+    def timing_enable(self, mask, max_launches=4096):
+        self._check(self._lib.fish_batch_timing_enable(self._h, int(mask), int(max_launches)))
+
+    def timing_read(self):
+        n = ctypes.c_int()
+        ms = ctypes.c_double()
+        self._check(self._lib.fish_batch_timing_read(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+
+class Server:
+    """Request loop over a batch: FIFO admission while the pool (the HBM
+    budget) has room, all resident boxes advanced together, finished boxes
+    retired into their output arrays."""
+
+    def __init__(self, pool_bytes, chunk_steps=8, max_boxes=4096, gamma=5.0 / 3.0, limiter=VANLEER,
+                 predictor_alpha=1.0, precision="fp32", gravity=False, hse=False, device=0, stream=None,
+                 use_torch_allocator=True):
+        lib = load_library()
+        self._lib = lib
+        p = _batch_params(self, pool_bytes, max_boxes, gamma, limiter, predictor_alpha, precision, gravity, hse,
+                          device, stream, use_torch_allocator)
+        self.params = p
+        self.gravity = bool(gravity)
+        h = ctypes.c_void_p()
+        rc = lib.fish_server_create(ctypes.byref(p), int(chunk_steps), ctypes.byref(h))
+        if rc != FISH_OK:
+            raise FishError(rc, "fish_server_create failed")
+        self._h = h
+        self._live = {}   # tag -> (request, input arrays, output dict) kept alive until completion
+        self._done = (ctypes.c_int64 * 4096)()
+        self._status = (ctypes.c_int32 * 4096)()
+
+    def _check(self, rc):
+        if rc != FISH_OK:
+            raise FishError(rc, self._lib.fish_server_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.fish_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, tag, st, nsteps, h=None, cfl=0.5, bc=(PERIODIC,) * 3):
+        cell = np.ascontiguousarray(st["cell"], dtype=np.float64)
+        _, nz, ny, nx = cell.shape
+        arrs = [cell] + [np.ascontiguousarray(st[k], dtype=np.float64) for k in ("bx", "by", "bz")]
+        phi = np.ascontiguousarray(st["phi"], dtype=np.float64) if self.gravity else None
+        out = {"cell": np.empty((5, nz, ny, nx)), "bx": np.empty((nz, ny, nx + 1)),
+               "by": np.empty((nz, ny + 1, nx)), "bz": np.empty((nz + 1, ny, nx))}
+        r = Request()
+        r.box = _geom((nx, ny, nz), h, cfl, bc)
+        r.nsteps = int(nsteps)
+        r.cell5, r.bx, r.by, r.bz = (_dptr(a) for a in arrs)
+        r.phi = _dptr(phi)
+        r.out_cell5, r.out_bx, r.out_by, r.out_bz = (_dptr(out[k]) for k in ("cell", "bx", "by", "bz"))
+        r.tag = int(tag)
+        self._check(self._lib.fish_server_submit(self._h, ctypes.byref(r)))
+        self._live[int(tag)] = (r, arrs, phi, out)
+
+    def pump(self):
+        """One scheduling round; returns [(tag, status, output state)] of the
+        requests that completed."""
+        n = ctypes.c_int()
+        self._check(self._lib.fish_server_pump(self._h, self._done, self._status, len(self._done), ctypes.byref(n)))
+        res = []
+        for i in range(n.value):
+            tag = int(self._done[i])
+            _, _, _, out = self._live.pop(tag)
+            res.append((tag, int(self._status[i]), out))
+        return res
+
+    def stats(self):
+        q, r, f, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t(), ctypes.c_int64()
+        self._check(self._lib.fish_server_stats(self._h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(f),
+                                                ctypes.byref(c)))
+        return {"queued": q.value, "resident": r.value, "pool_free": f.value, "cell_steps": c.value}
+
+    def batch_autotune(self, reps=3):
+        b = self._lib.fish_server_batch(self._h)
+        t = (ctypes.c_int32 * 7)()
+        rc = self._lib.fish_batch_autotune(b, int(reps), t)
+        if rc != FISH_OK:
+            raise FishError(rc, self._lib.fish_batch_last_error(b).decode())
+        return dict(zip(KINDS, list(t)))
+
+    def use_graph(self, on=True):
+        b = self._lib.fish_server_batch(self._h)
+        rc = self._lib.fish_batch_use_graph(b, int(bool(on)))
+        if rc != FISH_OK:
+            raise FishError(rc, self._lib.fish_batch_last_error(b).decode())

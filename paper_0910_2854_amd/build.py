@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfish.so")
-SOURCES = [os.path.join(HERE, "csrc", "fish.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fish.hip", "engine.hip", "server.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

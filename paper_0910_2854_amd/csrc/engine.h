@@ -1,0 +1,167 @@
+// engine.h -- host engine of the FISH split MHD step on gfx950: one stream,
+// one pool per field (two buffers each), any number of boxes at element
+// offsets of the pools, a device box table and per-kernel work lists, and
+// the sequencing of the sub-operators.  The single-box context and the batch
+// of the C interface are both an Engine; every step of the arithmetic runs in
+// the kernels of sweeps.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "layout.h"
+
+namespace fish {
+
+struct DeviceBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+// One box of the engine (host side).
+struct HostBox {
+  bool used = false;
+  bool have_state = false;
+  bool cfl_fresh = false;   // its Scalars::cmax_bits holds the CFL speed of its state
+  int n[3]{};
+  int o[3]{};               // extra layer on outflow axes
+  int bc[3]{};
+  double h[3]{};
+  double cfl = 0.5;
+  long long st[3]{};        // element strides (1, sy, sz)
+  long long nelem = 0;      // elements per array
+  long long off = 0;        // element offset in every pool
+  long long reserved = 0;   // elements reserved in the pools (aligned)
+};
+
+struct EngineConfig {
+  int precision = 0;        // 0 FP64, 1 FP32
+  double gamma = 5.0 / 3.0;
+  double alpha = 1.0;
+  int limiter = 1;
+  int gravity = 0;
+  int hse = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* (*alloc)(size_t, void*, void*) = nullptr;
+  void (*free)(void*, size_t, void*, void*) = nullptr;
+  void* alloc_user = nullptr;
+};
+
+// Tuning targets per kernel kind: stream positions per wave for the x kinds
+// (whole rows of the box fill it), the segment length along the sweep for
+// the y/z kinds, cells per lane for the CFL check.
+struct Tuning {
+  int target[K_NUM];
+};
+Tuning default_tuning();
+
+class Engine {
+ public:
+  EngineConfig cfg;
+  bool live = false;        // init ran; release() frees once
+  size_t esize = 8;
+  std::string err;
+  size_t device_bytes = 0;
+
+  // pools: [buffer][field] with fields rho, m_x, m_y, m_z, E, b_x, b_y, b_z
+  long long cap = 0;  // elements per pool
+  DeviceBuf pool[2][8];
+  DeviceBuf phi;
+  int cur[8]{};
+  std::map<long long, long long> free_list;  // offset -> length (elements)
+
+  std::vector<HostBox> boxes;  // slots
+  DeviceBuf scal;              // Scalars per slot
+  DeviceBuf partial, diag_out;
+  int npartial = 1024;
+
+  // device table and work lists (rebuilt when the set of boxes changes)
+  DeviceBuf table;
+  DeviceBuf lists[K_NUM];
+  int nwaves[K_NUM]{};
+  std::vector<int> table_slots;
+  bool dirty = true;
+  Tuning tuning = default_tuning();
+
+  // graph of one CFL-stepped double step for the current table
+  bool use_graph = false;
+  bool graph_ok = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+
+  bool last_fluid_cfl = false;
+
+  // measurement hook
+  int timing_mask = 0;
+  int timing_max = 0;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  int ev_used = 0;
+
+  ~Engine();
+  int fail(int code, const std::string& msg);
+  int init(const EngineConfig& c, long long cap_elems, int max_boxes);
+  void release();
+  int set_device();
+
+  // boxes
+  static int validate_box(const int n[3], const double h[3], const int bc[3], double cfl);
+  long long box_elems(const int n[3], const int bc[3]) const;
+  int add_box(const int n[3], const double h[3], const int bc[3], double cfl, int* slot);
+  int remove_box(int slot);
+  int upload(int slot, const double* cell5, const double* bx, const double* by, const double* bz,
+             const double* phi_in);
+  int download(int slot, double* cell5, double* bx, double* by, double* bz);
+  int read_scalars(int slot, Scalars* out);
+  int count() const;
+  long long free_elems() const;
+
+  // stepping
+  int ensure_table();
+  int check_cfl_all();
+  int strang_step(double dt);               // every box of the table
+  int steps(int nsteps);                    // CFL-stepped double steps, graph when enabled
+  int sweep(int slot, int op, int dir, double dt);
+  int diagnostics(int slot, double* out10);
+  int autotune(int reps, int* chosen);
+  int set_graph(bool on);
+
+ private:
+  int dev_alloc(DeviceBuf& b, size_t bytes);
+  void dev_free(DeviceBuf& b);
+  int launch_check();
+  int run_sub(int op, int d);
+  int enqueue_step_cfl();                   // the launches of one CFL-stepped double step
+  void invalidate_graph();
+  int build_lists();
+  template <typename T>
+  int sub_operator(int op, int d);
+  template <typename T, int D>
+  int fluid_dispatch();
+  template <typename T, int D, int LIM>
+  void fluid_dispatch_lim();
+  template <typename T, int D, bool GRAV, bool HSE, int LIM>
+  void launch_fluid();
+  template <typename T, int D>
+  int field_sweep();
+  template <typename T, int D, int LIM>
+  int field_sweep_lim();
+  template <typename T>
+  int launch_check_cfl();
+  template <typename T>
+  int launch_diag(int slot);
+  template <typename T>
+  int upload_t(int slot, const double* cell5, const double* bx, const double* by, const double* bz,
+               const double* phi_in);
+  template <typename T>
+  int download_t(int slot, double* cell5, double* bx, double* by, double* bz);
+  friend struct TimedLaunch;
+};
+
+// Run the lane-shift self-test kernel on `device` (out128: host, 128 values).
+int selftest_lane_shift(int device, float* out128);
+
+}  // namespace fish

@@ -1,0 +1,874 @@
+// engine.hip -- the host engine of engine.h: device pools and their offset
+// allocator, box upload/download, the box table and work lists, the
+// sequencing of the symmetric double step of Eqs. (12)-(13), its capture in
+// a HIP graph, and the autotuner of the work-list shapes.
+#include "engine.h"
+
+#include "sweeps.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace fish {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr long long kAlign = 64;  // box offsets in elements (256 B in FP32)
+
+unsigned grid_for(long long threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(3, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+Tuning default_tuning() {
+  Tuning t;
+  t.target[K_FLUID_X] = 768;
+  t.target[K_FIELD_X] = 768;
+  t.target[K_FLUID_Y] = t.target[K_FLUID_Z] = 64;
+  t.target[K_FIELD_Y] = t.target[K_FIELD_Z] = 64;
+  t.target[K_CHECK] = 16;
+  return t;
+}
+
+// Bracket one kernel launch with events when its class is being timed
+// (classes: 1 fluid, 2 field, 8 CFL check).
+struct TimedLaunch {
+  Engine* e;
+  int idx = -1;
+  TimedLaunch(Engine* eng, int cls) : e(eng) {
+    if ((e->timing_mask & cls) && e->ev_used < e->timing_max) {
+      idx = e->ev_used++;
+      (void)hipEventRecord(e->ev_start[idx], e->cfg.stream);
+    }
+  }
+  ~TimedLaunch() {
+    if (idx >= 0) (void)hipEventRecord(e->ev_stop[idx], e->cfg.stream);
+  }
+};
+
+Engine::~Engine() { release(); }
+
+int Engine::fail(int code, const std::string& msg) {
+  err = msg;
+  return code;
+}
+
+int Engine::set_device() {
+  HIP_TRY(hipSetDevice(cfg.device));
+  return 0;
+}
+
+int Engine::dev_alloc(DeviceBuf& b, size_t bytes) {
+  b.bytes = bytes;
+  if (bytes == 0) {
+    b.ptr = nullptr;
+    return 0;
+  }
+  if (cfg.alloc) {
+    b.ptr = cfg.alloc(bytes, cfg.stream, cfg.alloc_user);
+    if (!b.ptr) return fail(2, "allocator callback returned NULL");
+  } else {
+    hipError_t e = hipMalloc(&b.ptr, bytes);
+    if (e != hipSuccess) {
+      b.ptr = nullptr;
+      return fail(2, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+  }
+  device_bytes += bytes;
+  return 0;
+}
+
+void Engine::dev_free(DeviceBuf& b) {
+  if (!b.ptr) return;
+  if (cfg.alloc) {
+    if (cfg.free) cfg.free(b.ptr, b.bytes, cfg.stream, cfg.alloc_user);
+  } else {
+    (void)hipFree(b.ptr);
+  }
+  device_bytes -= b.bytes;
+  b.ptr = nullptr;
+  b.bytes = 0;
+}
+
+int Engine::launch_check() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(3, std::string("kernel launch: ") + hipGetErrorString(e));
+  return 0;
+}
+
+int Engine::init(const EngineConfig& c, long long cap_elems, int max_boxes) {
+  cfg = c;
+  live = true;
+  esize = cfg.precision == 0 ? 8 : 4;
+  cap = (cap_elems + kAlign - 1) / kAlign * kAlign;
+  int rc = set_device();
+  if (rc) return rc;
+  const size_t bytes = (size_t)cap * esize;
+  for (int b = 0; b < 2 && !rc; ++b)
+    for (int f = 0; f < 8 && !rc; ++f) rc = dev_alloc(pool[b][f], bytes);
+  if (!rc && cfg.gravity) rc = dev_alloc(phi, bytes);
+  if (!rc) rc = dev_alloc(scal, sizeof(Scalars) * (size_t)max_boxes);
+  if (!rc) rc = dev_alloc(table, sizeof(BoxDesc) * (size_t)max_boxes);
+  if (!rc) rc = dev_alloc(partial, (size_t)npartial * 10 * sizeof(double));
+  if (!rc) rc = dev_alloc(diag_out, 16 * sizeof(double));
+  if (rc) return rc;
+  boxes.assign(max_boxes, HostBox());
+  free_list.clear();
+  free_list[0] = cap;
+  for (int s = 0; s < max_boxes; ++s) {
+    hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(1), 0, cfg.stream, (Scalars*)scal.ptr + s, 0.0, 0);
+  }
+  if ((rc = launch_check())) return rc;
+  HIP_TRY(hipStreamSynchronize(cfg.stream));
+  return 0;
+}
+
+void Engine::release() {
+  if (!live) return;
+  live = false;
+  (void)hipSetDevice(cfg.device);
+  (void)hipStreamSynchronize(cfg.stream);
+  invalidate_graph();
+  for (auto e : ev_start) (void)hipEventDestroy(e);
+  for (auto e : ev_stop) (void)hipEventDestroy(e);
+  ev_start.clear();
+  ev_stop.clear();
+  for (int b = 0; b < 2; ++b)
+    for (int f = 0; f < 8; ++f) dev_free(pool[b][f]);
+  dev_free(phi);
+  dev_free(scal);
+  dev_free(table);
+  for (int k = 0; k < K_NUM; ++k) dev_free(lists[k]);
+  dev_free(partial);
+  dev_free(diag_out);
+}
+
+void Engine::invalidate_graph() {
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (graph) (void)hipGraphDestroy(graph);
+  gexec = nullptr;
+  graph = nullptr;
+  graph_ok = false;
+}
+
+// ------------------------------------------------------------ boxes
+int Engine::validate_box(const int n[3], const double h[3], const int bc[3], double cfl) {
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 1 || n[a] > (1 << 20)) return 1;
+    if (!(h[a] > 0.0) || !std::isfinite(h[a])) return 1;
+    if (bc[a] != 0 && bc[a] != 1) return 1;
+  }
+  if (!(cfl > 0.0) || cfl > 1.0) return 1;
+  return 0;
+}
+
+long long Engine::box_elems(const int n[3], const int bc[3]) const {
+  return (long long)(n[0] + bc[0]) * (n[1] + bc[1]) * (n[2] + bc[2]);
+}
+
+int Engine::count() const {
+  int c = 0;
+  for (const auto& b : boxes) c += b.used ? 1 : 0;
+  return c;
+}
+
+long long Engine::free_elems() const {
+  long long f = 0;
+  for (const auto& kv : free_list) f += kv.second;
+  return f;
+}
+
+int Engine::add_box(const int n[3], const double h[3], const int bc[3], double cfl, int* slot_out) {
+  if (validate_box(n, h, bc, cfl)) return fail(1, "invalid box geometry");
+  const long long ne = box_elems(n, bc);
+  if ((unsigned long long)ne * esize >= (1ull << 32))
+    return fail(5, "each array of a box must stay below 4 GiB (32-bit byte offsets)");
+  int slot = -1;
+  for (int s = 0; s < (int)boxes.size(); ++s)
+    if (!boxes[s].used) {
+      slot = s;
+      break;
+    }
+  if (slot < 0) return fail(2, "no free box slot");
+  const long long need = (ne + kAlign - 1) / kAlign * kAlign;
+  // first fit over the free ranges
+  auto it = free_list.begin();
+  for (; it != free_list.end(); ++it)
+    if (it->second >= need) break;
+  if (it == free_list.end()) return fail(2, "pool has no free range large enough for the box");
+  const long long off = it->first, len = it->second;
+  free_list.erase(it);
+  if (len > need) free_list[off + need] = len - need;
+  HostBox& b = boxes[slot];
+  b = HostBox();
+  b.used = true;
+  for (int a = 0; a < 3; ++a) {
+    b.n[a] = n[a];
+    b.bc[a] = bc[a];
+    b.o[a] = bc[a] == 1 ? 1 : 0;
+    b.h[a] = h[a];
+  }
+  b.cfl = cfl;
+  b.st[0] = 1;
+  b.st[1] = n[0] + b.o[0];
+  b.st[2] = b.st[1] * (n[1] + b.o[1]);
+  b.nelem = ne;
+  b.off = off;
+  b.reserved = need;
+  dirty = true;
+  invalidate_graph();
+  *slot_out = slot;
+  return 0;
+}
+
+int Engine::remove_box(int slot) {
+  if (slot < 0 || slot >= (int)boxes.size() || !boxes[slot].used) return fail(1, "no such box");
+  int rc = set_device();
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(cfg.stream));  // no launch in flight reads its range
+  HostBox& b = boxes[slot];
+  long long off = b.off, len = b.reserved;
+  // return the range and merge with its neighbours
+  auto nx = free_list.lower_bound(off);
+  if (nx != free_list.end() && nx->first == off + len) {
+    len += nx->second;
+    free_list.erase(nx);
+  }
+  auto pv = free_list.lower_bound(off);
+  if (pv != free_list.begin()) {
+    --pv;
+    if (pv->first + pv->second == off) {
+      off = pv->first;
+      len += pv->second;
+      free_list.erase(pv);
+    }
+  }
+  free_list[off] = len;
+  b = HostBox();
+  dirty = true;
+  invalidate_graph();
+  return 0;
+}
+
+// Host-side repacking between the interface layout and the device layout.
+// Face array `a` (0 = x) along its own normal: the interface carries n+1
+// faces; the device stores n (periodic) or n+1 (outflow).
+template <typename T>
+static void pack_cell(const HostBox& c, const double* src, std::vector<T>& dst) {
+  const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i)
+        dst[i + c.st[1] * j + c.st[2] * k] = (T)src[(size_t)i + (size_t)nx * (j + (size_t)ny * k)];
+}
+
+template <typename T>
+static void pack_face(const HostBox& c, int a, const double* src, std::vector<T>& dst) {
+  int m[3] = {c.n[0], c.n[1], c.n[2]};  // input extents
+  m[a] += 1;
+  int keep[3] = {c.n[0], c.n[1], c.n[2]};  // stored faces
+  keep[a] += c.o[a];
+  for (int k = 0; k < keep[2]; ++k)
+    for (int j = 0; j < keep[1]; ++j)
+      for (int i = 0; i < keep[0]; ++i)
+        dst[i + c.st[1] * j + c.st[2] * k] = (T)src[(size_t)i + (size_t)m[0] * (j + (size_t)m[1] * k)];
+}
+
+template <typename T>
+static void unpack_cell(const HostBox& c, const std::vector<T>& src, double* dst, size_t field_off) {
+  const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i)
+        dst[field_off + (size_t)i + (size_t)nx * (j + (size_t)ny * k)] = (double)src[i + c.st[1] * j + c.st[2] * k];
+}
+
+template <typename T>
+static void unpack_face(const HostBox& c, int a, const std::vector<T>& src, double* dst) {
+  int m[3] = {c.n[0], c.n[1], c.n[2]};
+  m[a] += 1;
+  for (int k = 0; k < m[2]; ++k)
+    for (int j = 0; j < m[1]; ++j)
+      for (int i = 0; i < m[0]; ++i) {
+        int q[3] = {i, j, k};
+        if (c.bc[a] == 0 && q[a] == c.n[a]) q[a] = 0;  // face n is face 0
+        dst[(size_t)i + (size_t)m[0] * (j + (size_t)m[1] * k)] = (double)src[q[0] + c.st[1] * q[1] + c.st[2] * q[2]];
+      }
+}
+
+template <typename T>
+int Engine::upload_t(int slot, const double* cell5, const double* bx, const double* by, const double* bz,
+                     const double* phi_in) {
+  const HostBox& c = boxes[slot];
+  std::vector<T> h((size_t)c.nelem, T(0));
+  const size_t nc = (size_t)c.n[0] * c.n[1] * c.n[2];
+  const size_t bytes = (size_t)c.nelem * sizeof(T);
+  for (int f = 0; f < 5; ++f) {
+    std::fill(h.begin(), h.end(), T(0));
+    pack_cell<T>(c, cell5 + f * nc, h);
+    HIP_TRY(hipMemcpyAsync((T*)pool[cur[f]][f].ptr + c.off, h.data(), bytes, hipMemcpyHostToDevice, cfg.stream));
+    HIP_TRY(hipStreamSynchronize(cfg.stream));
+  }
+  const double* bsrc[3] = {bx, by, bz};
+  for (int a = 0; a < 3; ++a) {
+    std::fill(h.begin(), h.end(), T(0));
+    pack_face<T>(c, a, bsrc[a], h);
+    HIP_TRY(hipMemcpyAsync((T*)pool[cur[5 + a]][5 + a].ptr + c.off, h.data(), bytes, hipMemcpyHostToDevice,
+                           cfg.stream));
+    HIP_TRY(hipStreamSynchronize(cfg.stream));
+  }
+  if (cfg.gravity) {
+    std::fill(h.begin(), h.end(), T(0));
+    pack_cell<T>(c, phi_in, h);
+    HIP_TRY(hipMemcpyAsync((T*)phi.ptr + c.off, h.data(), bytes, hipMemcpyHostToDevice, cfg.stream));
+    HIP_TRY(hipStreamSynchronize(cfg.stream));
+  }
+  return 0;
+}
+
+int Engine::upload(int slot, const double* cell5, const double* bx, const double* by, const double* bz,
+                   const double* phi_in) {
+  if (slot < 0 || slot >= (int)boxes.size() || !boxes[slot].used) return fail(1, "no such box");
+  int rc = set_device();
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(cfg.stream));
+  rc = esize == 8 ? upload_t<double>(slot, cell5, bx, by, bz, phi_in) : upload_t<float>(slot, cell5, bx, by, bz, phi_in);
+  if (rc) return rc;
+  hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(1), 0, cfg.stream, (Scalars*)scal.ptr + slot, 0.0, 0);
+  if ((rc = launch_check())) return rc;
+  boxes[slot].have_state = true;
+  boxes[slot].cfl_fresh = false;
+  if (!dirty && !table_slots.empty()) {
+    // the table lists only boxes with a state
+    bool listed = std::find(table_slots.begin(), table_slots.end(), slot) != table_slots.end();
+    if (!listed) dirty = true;
+  } else {
+    dirty = true;
+  }
+  return 0;
+}
+
+template <typename T>
+int Engine::download_t(int slot, double* cell5, double* bx, double* by, double* bz) {
+  const HostBox& c = boxes[slot];
+  std::vector<T> h((size_t)c.nelem);
+  const size_t nc = (size_t)c.n[0] * c.n[1] * c.n[2];
+  const size_t bytes = (size_t)c.nelem * sizeof(T);
+  if (cell5)
+    for (int f = 0; f < 5; ++f) {
+      HIP_TRY(hipMemcpyAsync(h.data(), (T*)pool[cur[f]][f].ptr + c.off, bytes, hipMemcpyDeviceToHost, cfg.stream));
+      HIP_TRY(hipStreamSynchronize(cfg.stream));
+      unpack_cell<T>(c, h, cell5, f * nc);
+    }
+  double* bdst[3] = {bx, by, bz};
+  for (int a = 0; a < 3; ++a) {
+    if (!bdst[a]) continue;
+    HIP_TRY(hipMemcpyAsync(h.data(), (T*)pool[cur[5 + a]][5 + a].ptr + c.off, bytes, hipMemcpyDeviceToHost,
+                           cfg.stream));
+    HIP_TRY(hipStreamSynchronize(cfg.stream));
+    unpack_face<T>(c, a, h, bdst[a]);
+  }
+  return 0;
+}
+
+int Engine::download(int slot, double* cell5, double* bx, double* by, double* bz) {
+  if (slot < 0 || slot >= (int)boxes.size() || !boxes[slot].used) return fail(1, "no such box");
+  int rc = set_device();
+  if (rc) return rc;
+  return esize == 8 ? download_t<double>(slot, cell5, bx, by, bz) : download_t<float>(slot, cell5, bx, by, bz);
+}
+
+int Engine::read_scalars(int slot, Scalars* out) {
+  HIP_TRY(hipMemcpyAsync(out, (Scalars*)scal.ptr + slot, sizeof(Scalars), hipMemcpyDeviceToHost, cfg.stream));
+  HIP_TRY(hipStreamSynchronize(cfg.stream));
+  return 0;
+}
+
+// ------------------------------------------------------------ work lists
+static long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
+
+// Waves of one box in the list of one kind, and the per-box parameter.
+static long long kind_waves(const HostBox& b, int kind, int target, int* par) {
+  switch (kind) {
+    case K_FLUID_X: {
+      const int rpw = std::max(1, target / (b.n[0] + 6));
+      *par = rpw;
+      return ceil_div((long long)b.n[1] * b.n[2], rpw);
+    }
+    case K_FIELD_X: {
+      const int rpw = std::max(1, target / (b.n[0] + 8));
+      *par = rpw;
+      return ceil_div((long long)(b.n[1] + b.o[1]) * (b.n[2] + b.o[2]), rpw);
+    }
+    case K_FLUID_Y:
+    case K_FLUID_Z: {
+      const int D = kind - K_FLUID_X;
+      const int seg = std::max(1, std::min(target, b.n[D]));
+      *par = seg;
+      return ceil_div((long long)b.n[0] * b.n[3 - D], 64) * ceil_div(b.n[D], seg);
+    }
+    case K_FIELD_Y:
+    case K_FIELD_Z: {
+      const int D = kind - K_FIELD_X;
+      const int seg = std::max(1, std::min(target, b.n[D]));
+      *par = seg;
+      return ceil_div((long long)(b.n[0] + b.o[0]) * (b.n[3 - D] + b.o[3 - D]), 64) * ceil_div(b.n[D], seg);
+    }
+    default: {
+      const int cpl = std::max(1, target);
+      *par = cpl;
+      return ceil_div((long long)b.n[0] * b.n[1] * b.n[2], 64ll * cpl);
+    }
+  }
+}
+
+int Engine::build_lists() {
+  table_slots.clear();
+  for (int s = 0; s < (int)boxes.size(); ++s)
+    if (boxes[s].used && boxes[s].have_state) table_slots.push_back(s);
+  const int nb = (int)table_slots.size();
+  std::vector<BoxDesc> desc(nb);
+  std::vector<int> list[K_NUM];
+  for (int t = 0; t < nb; ++t) {
+    const HostBox& b = boxes[table_slots[t]];
+    BoxDesc& d = desc[t];
+    std::memset(&d, 0, sizeof d);
+    for (int a = 0; a < 3; ++a) {
+      d.g.n[a] = b.n[a];
+      d.g.bc[a] = b.bc[a];
+      d.g.st[a] = b.st[a];
+      d.g.h[a] = b.h[a];
+    }
+    d.off = b.off;
+    d.cfl = b.cfl;
+    d.slot = table_slots[t];
+    for (int k = 0; k < K_NUM; ++k) {
+      int par = 1;
+      const long long w = kind_waves(b, k, tuning.target[k], &par);
+      if ((long long)list[k].size() + w >= (1ll << 31) / 64)
+        return fail(5, "work list exceeds the launch size");
+      d.wave0[k] = (int)list[k].size();
+      d.par[k] = par;
+      list[k].insert(list[k].end(), (size_t)w, t);
+    }
+  }
+  int rc = set_device();
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(cfg.stream));  // nothing in flight reads the old lists
+  if (nb > 0) HIP_TRY(hipMemcpy(table.ptr, desc.data(), sizeof(BoxDesc) * nb, hipMemcpyHostToDevice));
+  for (int k = 0; k < K_NUM; ++k) {
+    const size_t bytes = list[k].size() * sizeof(int);
+    if (lists[k].bytes < bytes) {
+      dev_free(lists[k]);
+      if ((rc = dev_alloc(lists[k], bytes + bytes / 4))) return rc;
+    }
+    if (bytes) HIP_TRY(hipMemcpy(lists[k].ptr, list[k].data(), bytes, hipMemcpyHostToDevice));
+    nwaves[k] = (int)list[k].size();
+  }
+  dirty = false;
+  invalidate_graph();
+  return 0;
+}
+
+int Engine::ensure_table() { return dirty ? build_lists() : 0; }
+
+static WorkList make_wl(const Engine* e, int kind) {
+  WorkList w;
+  w.boxes = static_cast<const BoxDesc*>(e->table.ptr);
+  w.wave_box = static_cast<const int*>(e->lists[kind].ptr);
+  w.nwaves = e->nwaves[kind];
+  return w;
+}
+
+// ------------------------------------------------------------ sub-operators
+template <typename T, int D, bool GRAV, bool HSE, int LIM>
+void Engine::launch_fluid() {
+  FluidLaunch<T> L;
+  for (int k = 0; k < 5; ++k) {
+    L.u[k] = (const T*)pool[cur[k]][k].ptr;
+    L.uo[k] = (T*)pool[1 - cur[k]][k].ptr;
+  }
+  for (int k = 0; k < 3; ++k) L.b[k] = (const T*)pool[cur[5 + k]][5 + k].ptr;
+  L.phi = (const T*)phi.ptr;
+  L.gamma = cfg.gamma;
+  L.alpha = cfg.alpha;
+  L.wl = make_wl(this, K_FLUID_X + D);
+  L.sc = (Scalars*)scal.ptr;
+  if (L.wl.nwaves == 0) return;
+  const dim3 grid(grid_for((long long)L.wl.nwaves * 64));
+  TimedLaunch tl(this, 1);
+  if (D == 0) {
+    if (last_fluid_cfl)
+      hipLaunchKernelGGL((fluid_lanes_kernel<T, GRAV, HSE, LIM, true>), grid, dim3(kBlock), 0, cfg.stream, L);
+    else
+      hipLaunchKernelGGL((fluid_lanes_kernel<T, GRAV, HSE, LIM, false>), grid, dim3(kBlock), 0, cfg.stream, L);
+  } else {
+    constexpr int DD = D == 0 ? 1 : D;
+    hipLaunchKernelGGL((fluid_strided_kernel<T, DD, GRAV, HSE, LIM>), grid, dim3(kBlock), 0, cfg.stream, L);
+  }
+}
+
+template <typename T, int D, int LIM>
+void Engine::fluid_dispatch_lim() {
+  if (!cfg.gravity)
+    launch_fluid<T, D, false, false, LIM>();
+  else if (!cfg.hse)
+    launch_fluid<T, D, true, false, LIM>();
+  else
+    launch_fluid<T, D, true, true, LIM>();
+}
+
+template <typename T, int D>
+int Engine::fluid_dispatch() {
+  if (cfg.limiter == 0)
+    fluid_dispatch_lim<T, D, 0>();
+  else
+    fluid_dispatch_lim<T, D, 1>();
+  for (int k = 0; k < 5; ++k) cur[k] = 1 - cur[k];
+  return launch_check();
+}
+
+template <typename T, int D, int LIM>
+int Engine::field_sweep_lim() {
+  const int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  FieldLaunch<T> L;
+  L.rho = (const T*)pool[cur[0]][0].ptr;
+  L.md = (const T*)pool[cur[1 + D]][1 + D].ptr;
+  L.bt[0] = (const T*)pool[cur[5 + t1]][5 + t1].ptr;
+  L.bt[1] = (const T*)pool[cur[5 + t2]][5 + t2].ptr;
+  L.bd = (const T*)pool[cur[5 + D]][5 + D].ptr;
+  L.bto[0] = (T*)pool[1 - cur[5 + t1]][5 + t1].ptr;
+  L.bto[1] = (T*)pool[1 - cur[5 + t2]][5 + t2].ptr;
+  L.bdo = (T*)pool[1 - cur[5 + D]][5 + D].ptr;
+  L.wl = make_wl(this, K_FIELD_X + D);
+  L.sc = (Scalars*)scal.ptr;
+  if (L.wl.nwaves > 0) {
+    const dim3 grid(grid_for((long long)L.wl.nwaves * 64));
+    TimedLaunch tl(this, 2);
+    if (D == 0) {
+      hipLaunchKernelGGL((field_lanes_kernel<T, LIM>), grid, dim3(kBlock), 0, cfg.stream, L);
+    } else {
+      constexpr int DD = D == 0 ? 1 : D;
+      hipLaunchKernelGGL((field_strided_kernel<T, DD, LIM>), grid, dim3(kBlock), 0, cfg.stream, L);
+    }
+  }
+  for (int f = 5; f < 8; ++f) cur[f] = 1 - cur[f];
+  return launch_check();
+}
+
+template <typename T, int D>
+int Engine::field_sweep() {
+  return cfg.limiter == 0 ? field_sweep_lim<T, D, 0>() : field_sweep_lim<T, D, 1>();
+}
+
+template <typename T>
+int Engine::sub_operator(int op, int d) {
+  if (op == 0) {
+    switch (d) {
+      case 0: return fluid_dispatch<T, 0>();
+      case 1: return fluid_dispatch<T, 1>();
+      default: return fluid_dispatch<T, 2>();
+    }
+  }
+  switch (d) {
+    case 0: return field_sweep<T, 0>();
+    case 1: return field_sweep<T, 1>();
+    default: return field_sweep<T, 2>();
+  }
+}
+
+int Engine::run_sub(int op, int d) { return esize == 8 ? sub_operator<double>(op, d) : sub_operator<float>(op, d); }
+
+template <typename T>
+int Engine::launch_check_cfl() {
+  CheckLaunch<T> L;
+  for (int k = 0; k < 5; ++k) L.u[k] = (const T*)pool[cur[k]][k].ptr;
+  for (int k = 0; k < 3; ++k) L.b[k] = (const T*)pool[cur[5 + k]][5 + k].ptr;
+  L.gamma = cfg.gamma;
+  L.wl = make_wl(this, K_CHECK);
+  L.sc = (Scalars*)scal.ptr;
+  const int nb = (int)table_slots.size();
+  if (nb == 0) return 0;
+  hipLaunchKernelGGL(reset_cmax_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream,
+                     (const BoxDesc*)table.ptr, nb, (Scalars*)scal.ptr);
+  if (L.wl.nwaves > 0) {
+    TimedLaunch tl(this, 8);
+    hipLaunchKernelGGL((check_cfl_kernel<T>), dim3(grid_for((long long)L.wl.nwaves * 64)), dim3(kBlock), 0,
+                       cfg.stream, L);
+  }
+  return launch_check();
+}
+
+int Engine::check_cfl_all() {
+  int rc = ensure_table();
+  if (rc) return rc;
+  rc = esize == 8 ? launch_check_cfl<double>() : launch_check_cfl<float>();
+  if (rc) return rc;
+  for (int s : table_slots) boxes[s].cfl_fresh = true;
+  return 0;
+}
+
+// The launches of one double step with every box's CFL step: dt from the
+// CFL speed of the current state, the twelve sub-operators of Eqs. (12)-(13)
+// in symmetric order, the CFL speed of the new state reduced by the last
+// sweep, t += 2 dt.
+int Engine::enqueue_step_cfl() {
+  const int nb = (int)table_slots.size();
+  const BoxDesc* tb = (const BoxDesc*)table.ptr;
+  Scalars* sc = (Scalars*)scal.ptr;
+  int rc;
+  hipLaunchKernelGGL(finalize_dt_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream, tb, nb, sc);
+  if ((rc = launch_check())) return rc;
+  for (int d = 0; d < 3; ++d) {
+    if ((rc = run_sub(0, d))) return rc;
+    if ((rc = run_sub(1, d))) return rc;
+  }
+  for (int d = 2; d >= 1; --d) {
+    if ((rc = run_sub(1, d))) return rc;
+    if ((rc = run_sub(0, d))) return rc;
+  }
+  if ((rc = run_sub(1, 0))) return rc;
+  hipLaunchKernelGGL(reset_cmax_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream, tb, nb, sc);
+  last_fluid_cfl = true;
+  rc = run_sub(0, 0);
+  last_fluid_cfl = false;
+  if (rc) return rc;
+  hipLaunchKernelGGL(advance_time_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream, tb, nb, sc);
+  return launch_check();
+}
+
+int Engine::strang_step(double dt) {
+  int rc = set_device();
+  if (rc) return rc;
+  if ((rc = ensure_table())) return rc;
+  if (table_slots.empty()) return 0;
+  bool fresh = true;
+  for (int s : table_slots) fresh = fresh && boxes[s].cfl_fresh;
+  if (dt == 0.0) {
+    if (!fresh && (rc = check_cfl_all())) return rc;
+    if ((rc = enqueue_step_cfl())) return rc;
+  } else {
+    // a given step size (one box): every sub-operator of size dt
+    for (int s : table_slots) {
+      hipLaunchKernelGGL(set_dt_kernel, dim3(1), dim3(1), 0, cfg.stream, (Scalars*)scal.ptr + s, dt);
+    }
+    if ((rc = launch_check())) return rc;
+    for (int d = 0; d < 3; ++d) {
+      if ((rc = run_sub(0, d))) return rc;
+      if ((rc = run_sub(1, d))) return rc;
+    }
+    for (int d = 2; d >= 1; --d) {
+      if ((rc = run_sub(1, d))) return rc;
+      if ((rc = run_sub(0, d))) return rc;
+    }
+    if ((rc = run_sub(1, 0))) return rc;
+    const int nb = (int)table_slots.size();
+    hipLaunchKernelGGL(reset_cmax_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream,
+                       (const BoxDesc*)table.ptr, nb, (Scalars*)scal.ptr);
+    last_fluid_cfl = true;
+    rc = run_sub(0, 0);
+    last_fluid_cfl = false;
+    if (rc) return rc;
+    hipLaunchKernelGGL(advance_time_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream,
+                       (const BoxDesc*)table.ptr, nb, (Scalars*)scal.ptr);
+    if ((rc = launch_check())) return rc;
+  }
+  for (int s : table_slots) boxes[s].cfl_fresh = true;
+  return 0;
+}
+
+int Engine::set_graph(bool on) {
+  use_graph = on;
+  if (!on) invalidate_graph();
+  return 0;
+}
+
+// nsteps CFL-stepped double steps of every box.  With graphs on, the launches
+// of one step are captured once per table and replayed.
+int Engine::steps(int nsteps) {
+  int rc = set_device();
+  if (rc) return rc;
+  if ((rc = ensure_table())) return rc;
+  if (table_slots.empty() || nsteps <= 0) return 0;
+  bool fresh = true;
+  for (int s : table_slots) fresh = fresh && boxes[s].cfl_fresh;
+  if (!fresh && (rc = check_cfl_all())) return rc;
+  if (!use_graph || timing_mask) {
+    for (int i = 0; i < nsteps; ++i)
+      if ((rc = enqueue_step_cfl())) return rc;
+    return 0;
+  }
+  if (!graph_ok) {
+    // the buffer parity of every field is the same after a whole step, so
+    // one captured step can be replayed any number of times
+    int saved[8];
+    std::memcpy(saved, cur, sizeof cur);
+    HIP_TRY(hipStreamBeginCapture(cfg.stream, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_step_cfl();
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cfg.stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      std::memcpy(cur, saved, sizeof cur);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(3, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    for (int f = 0; f < 8; ++f)
+      if (cur[f] != saved[f]) {
+        (void)hipGraphDestroy(g);
+        return fail(3, "a captured step must return every field to its buffer");
+      }
+    graph = g;
+    e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      invalidate_graph();
+      return fail(3, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    graph_ok = true;
+  }
+  for (int i = 0; i < nsteps; ++i) HIP_TRY(hipGraphLaunch(gexec, cfg.stream));
+  return 0;
+}
+
+int Engine::sweep(int slot, int op, int dir, double dt) {
+  int rc = set_device();
+  if (rc) return rc;
+  if ((rc = ensure_table())) return rc;
+  hipLaunchKernelGGL(set_dt_kernel, dim3(1), dim3(1), 0, cfg.stream, (Scalars*)scal.ptr + slot, dt);
+  if ((rc = launch_check())) return rc;
+  for (int s : table_slots) boxes[s].cfl_fresh = false;
+  return run_sub(op, dir);
+}
+
+template <typename T>
+int Engine::launch_diag(int slot) {
+  const HostBox& b = boxes[slot];
+  DiagArgs<T> a;
+  for (int k = 0; k < 5; ++k) a.u[k] = (const T*)pool[cur[k]][k].ptr + b.off;
+  for (int k = 0; k < 3; ++k) a.b[k] = (const T*)pool[cur[5 + k]][5 + k].ptr + b.off;
+  for (int x = 0; x < 3; ++x) {
+    a.g.n[x] = b.n[x];
+    a.g.bc[x] = b.bc[x];
+    a.g.st[x] = b.st[x];
+    a.g.h[x] = b.h[x];
+  }
+  a.partial = static_cast<double*>(partial.ptr);
+  const long long ncell = (long long)b.n[0] * b.n[1] * b.n[2];
+  const int nblk = (int)std::min<long long>(npartial, std::max<long long>(1, ncell / 4096));
+  const long long per_block = (ncell + nblk - 1) / nblk;
+  hipLaunchKernelGGL((diag_partial_kernel<T>), dim3(nblk), dim3(kBlock), 0, cfg.stream, a, per_block);
+  const double vol = b.h[0] * b.h[1] * b.h[2];
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(1), 0, cfg.stream, static_cast<const double*>(partial.ptr),
+                     nblk, static_cast<double*>(diag_out.ptr), vol, b.h[1] * b.h[2], b.h[0] * b.h[2], b.h[0] * b.h[1]);
+  return launch_check();
+}
+
+int Engine::diagnostics(int slot, double* out10) {
+  int rc = set_device();
+  if (rc) return rc;
+  rc = esize == 8 ? launch_diag<double>(slot) : launch_diag<float>(slot);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(out10, diag_out.ptr, 10 * sizeof(double), hipMemcpyDeviceToHost, cfg.stream));
+  HIP_TRY(hipStreamSynchronize(cfg.stream));
+  return 0;
+}
+
+// Autotuner: for each sweep kind, time its kernel over the current table for
+// every candidate shape and keep the fastest.  The timed launches write the
+// idle buffers only (no buffer flips), so the state is unchanged.
+int Engine::autotune(int reps, int* chosen) {
+  int rc = set_device();
+  if (rc) return rc;
+  if ((rc = ensure_table())) return rc;
+  if (table_slots.empty()) return fail(1, "no box with a state to tune on");
+  bool fresh = true;
+  for (int s : table_slots) fresh = fresh && boxes[s].cfl_fresh;
+  if (!fresh && (rc = check_cfl_all())) return rc;
+  // a valid dt in every box for the timed sweeps
+  const int nb = (int)table_slots.size();
+  hipLaunchKernelGGL(finalize_dt_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream, (const BoxDesc*)table.ptr,
+                     nb, (Scalars*)scal.ptr);
+  if ((rc = launch_check())) return rc;
+  static const int lanes_c[] = {256, 384, 512, 768, 1024, 1536, 2048, 3072};
+  static const int seg_c[] = {8, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int saved_mask = timing_mask;
+  timing_mask = 0;
+  for (int kind = K_FLUID_X; kind <= K_FIELD_Z; ++kind) {
+    const bool lanes = kind == K_FLUID_X || kind == K_FIELD_X;
+    const int* cand = lanes ? lanes_c : seg_c;
+    const int ncand = lanes ? (int)(sizeof lanes_c / sizeof(int)) : (int)(sizeof seg_c / sizeof(int));
+    const int op = kind >= K_FIELD_X ? 1 : 0;
+    const int d = op ? kind - K_FIELD_X : kind - K_FLUID_X;
+    float best = 1e30f;
+    int best_t = tuning.target[kind];
+    int last_par_sig = -1;
+    for (int ci = 0; ci < ncand && !rc; ++ci) {
+      tuning.target[kind] = cand[ci];
+      // skip candidates that give every box the same shape as the previous one
+      int sig = 0;
+      for (int s : table_slots) {
+        int par = 0;
+        (void)kind_waves(boxes[s], kind, cand[ci], &par);
+        sig = sig * 31 + par;
+      }
+      if (sig == last_par_sig) continue;
+      last_par_sig = sig;
+      if ((rc = build_lists())) break;
+      int saved[8];
+      std::memcpy(saved, cur, sizeof cur);
+      if ((rc = run_sub(op, d))) break;  // warm-up
+      std::memcpy(cur, saved, sizeof cur);
+      (void)hipEventRecord(e0, cfg.stream);
+      for (int r = 0; r < reps && !rc; ++r) {
+        rc = run_sub(op, d);
+        std::memcpy(cur, saved, sizeof cur);
+      }
+      (void)hipEventRecord(e1, cfg.stream);
+      if (rc) break;
+      hipError_t e = hipEventSynchronize(e1);
+      if (e != hipSuccess) {
+        rc = fail(3, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        best_t = cand[ci];
+      }
+    }
+    tuning.target[kind] = best_t;
+    if (chosen) chosen[kind] = best_t;
+    if (rc) break;
+  }
+  timing_mask = saved_mask;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (chosen) chosen[K_CHECK] = tuning.target[K_CHECK];
+  dirty = true;
+  int rc2 = ensure_table();
+  return rc ? rc : rc2;
+}
+
+int selftest_lane_shift(int device, float* out128) {
+  if (hipSetDevice(device) != hipSuccess) return 3;
+  float* d = nullptr;
+  if (hipMalloc(&d, 128 * sizeof(float)) != hipSuccess) return 2;
+  hipLaunchKernelGGL(lane_shift_selftest_kernel, dim3(1), dim3(64), 0, nullptr, d);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpy(out128, d, 128 * sizeof(float), hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  return e == hipSuccess ? 0 : 3;
+}
+
+}  // namespace fish

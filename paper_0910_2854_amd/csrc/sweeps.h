@@ -22,25 +22,21 @@
 //     no row is transposed.
 #pragma once
 
+#include "layout.h"
 #include "physics.h"
 
 namespace fish {
 
-struct Geo {
-  int n[3];
-  int bc[3];          // 0 periodic, 1 outflow
-  long long st[3];    // element strides, st[0] = 1
-  double h[3];
-};
-
-// Device-resident step scalars.
-struct Scalars {
-  double dt;                    // step size of every sub-operator
-  double t;                     // simulation time
-  unsigned long long cmax_bits; // max CFL speed (FP64 bits; all values >= 0)
-  int status;                   // sticky: 1 = bad state seen
-  int pad;
-};
+// The wave's box and its wave index within the box; false past the list
+// (the whole wave exits together).
+template <int KIND>
+__device__ __forceinline__ bool work_item(const WorkList& wl, const BoxDesc*& d, int& lw) {
+  const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  if (wave >= wl.nwaves) return false;
+  d = wl.boxes + wl.wave_box[wave];
+  lw = wave - d->wave0[KIND];
+  return true;
+}
 
 // ------------------------------------------------------------ addressing
 // Load/store at a wave-uniform base pointer plus a 32-bit per-lane byte
@@ -200,6 +196,43 @@ struct FluidArgs {
   const Scalars* sc;
 };
 
+// Kernel arguments of a fluid sweep over a batch: the pools and the list.
+template <typename T>
+struct FluidLaunch {
+  const T* u[5];
+  T* uo[5];
+  const T* b[3];
+  const T* phi;
+  double gamma, alpha;
+  WorkList wl;
+  Scalars* sc;
+};
+
+// The per-box view of a launch (pointers at the box, its geometry and step
+// scalars).
+template <typename T, int KIND>
+__device__ __forceinline__ FluidArgs<T> fluid_view(const FluidLaunch<T>& L, const BoxDesc& d) {
+  FluidArgs<T> a;
+  const long long off = d.off;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    a.u[i] = L.u[i] + off;
+    a.uo[i] = L.uo[i] + off;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) a.b[i] = L.b[i] + off;
+  a.phi = L.phi ? L.phi + off : nullptr;
+  a.g = d.g;
+  a.gamma = L.gamma;
+  a.alpha = L.alpha;
+  const int D = KIND - K_FLUID_X;
+  a.seg = d.par[KIND];
+  a.nseg = (d.g.n[D] + a.seg - 1) / a.seg;
+  a.rows_per_wave = d.par[KIND];
+  a.sc = L.sc + d.slot;
+  return a;
+}
+
 template <typename T>
 __device__ __forceinline__ T load_phi(const T* phi, long long base, long long st, int s, int n, int bc) {
   if (s >= 0 && s < n) return phi[base + (long long)s * st];
@@ -351,9 +384,8 @@ __device__ __forceinline__ FluidConsts<T> fluid_consts(const FluidArgs<T>& a, in
 // every position and its boundary mapping along d) is uniform across the wave
 // and lives in scalar registers; each lane only adds its pencil offset.
 // Returns false for waves beyond the grid (the whole wave exits together).
-__device__ __forceinline__ bool strided_map(int P, int nseg, int& sg, int& p, bool& active) {
+__device__ __forceinline__ bool strided_map(int wave, int P, int nseg, int& sg, int& p, bool& active) {
   const int wps = (P + 63) >> 6;
-  const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   sg = wave / wps;
   if (sg >= nseg) return false;
   const int p0 = (wave - sg * wps) * 64 + (int)(threadIdx.x & 63);
@@ -364,16 +396,20 @@ __device__ __forceinline__ bool strided_map(int P, int nseg, int& sg, int& p, bo
 
 // Strided policy (D = y or z): one lane per pencil segment, lanes along x.
 template <typename T, int D, bool GRAV, bool HSE, int LIM>
-__global__ __launch_bounds__(256) void fluid_strided_kernel(FluidArgs<T> a) {
+__global__ __launch_bounds__(256) void fluid_strided_kernel(FluidLaunch<T> L) {
   static_assert(D != 0, "x sweeps use the lanes policy");
   constexpr int A = 0;  // lanes walk along x
   constexpr int O = 3 - D;
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const BoxDesc* d;
+  int lw;
+  if (!work_item<K_FLUID_X + D>(L.wl, d, lw)) return;
+  const FluidArgs<T> a = fluid_view<T, K_FLUID_X + D>(L, *d);
   const Geo& g = a.g;
   const int nA = g.n[A], nO = g.n[O], nD = g.n[D];
   int sg, p;
   bool active;
-  if (!strided_map(nA * nO, a.nseg, sg, p, active)) return;
+  if (!strided_map(lw, nA * nO, a.nseg, sg, p, active)) return;
   const int s0 = sg * a.seg;
   const int s1 = min(nD, s0 + a.seg);
   int c[3];
@@ -485,13 +521,17 @@ __device__ __forceinline__ void publish_cfl(double cmax, int bad, Scalars* sc) {
 // CFL the sweep also reduces the CFL speed of the state it writes (the last
 // sub-operator of a double step leaves the next step's time step ready).
 template <typename T, bool GRAV, bool HSE, int LIM, bool CFL>
-__global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidArgs<T> a) {
+__global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
   constexpr int D = 0;
+  const BoxDesc* d;
+  int lw;
+  if (!work_item<K_FLUID_X>(FL.wl, d, lw)) return;
+  const FluidArgs<T> a = fluid_view<T, K_FLUID_X>(FL, *d);
   const Geo& g = a.g;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const int L = nx + 6;                     // stream positions per row
   const long long nrows = (long long)ny * nz;
-  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const long long wave = lw;
   const int lane = threadIdx.x & 63;
   const long long r0 = wave * a.rows_per_wave;
   if (r0 >= nrows) return;  // whole wave exits together
@@ -598,6 +638,39 @@ struct FieldArgs {
   int rows_per_wave;       // lanes policy
   const Scalars* sc;
 };
+
+template <typename T>
+struct FieldLaunch {
+  const T* rho;
+  const T* md;
+  const T* bt[2];
+  const T* bd;
+  T* bto[2];
+  T* bdo;
+  WorkList wl;
+  Scalars* sc;
+};
+
+template <typename T, int KIND>
+__device__ __forceinline__ FieldArgs<T> field_view(const FieldLaunch<T>& L, const BoxDesc& d) {
+  FieldArgs<T> a;
+  const long long off = d.off;
+  a.rho = L.rho + off;
+  a.md = L.md + off;
+  a.bt[0] = L.bt[0] + off;
+  a.bt[1] = L.bt[1] + off;
+  a.bd = L.bd + off;
+  a.bto[0] = L.bto[0] + off;
+  a.bto[1] = L.bto[1] + off;
+  a.bdo = L.bdo + off;
+  a.g = d.g;
+  const int D = KIND - K_FIELD_X;
+  a.seg = d.par[KIND];
+  a.nseg = (d.g.n[D] + a.seg - 1) / a.seg;
+  a.rows_per_wave = d.par[KIND];
+  a.sc = L.sc + d.slot;
+  return a;
+}
 
 template <typename T>
 struct RowHist {
@@ -764,18 +837,22 @@ __device__ __forceinline__ void field_compute(const FieldIn<T>& in, const FieldC
 
 // Strided policy (d = y or z).
 template <typename T, int D, int LIM>
-__global__ __launch_bounds__(256) void field_strided_kernel(FieldArgs<T> a) {
+__global__ __launch_bounds__(256) void field_strided_kernel(FieldLaunch<T> FL) {
   static_assert(D != 0, "x sweeps use the lanes policy");
   constexpr int A = 0;
   constexpr int O = 3 - D;
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const BoxDesc* d;
+  int lw;
+  if (!work_item<K_FIELD_X + D>(FL.wl, d, lw)) return;
+  const FieldArgs<T> a = field_view<T, K_FIELD_X + D>(FL, *d);
   const Geo& g = a.g;
   const int nD = g.n[D];
   const int rA = g.n[A] + g.bc[A];  // outflow adds the face row n
   const int rO = g.n[O] + g.bc[O];
   int sg, p;
   bool active;
-  if (!strided_map(rA * rO, a.nseg, sg, p, active)) return;
+  if (!strided_map(lw, rA * rO, a.nseg, sg, p, active)) return;
   const int s0 = sg * a.seg;
   const int s1 = min(nD, s0 + a.seg);
   const bool last = (s1 == nD);
@@ -834,8 +911,12 @@ __global__ __launch_bounds__(256) void field_strided_kernel(FieldArgs<T> a) {
 // Lanes policy (d = x): waves stream whole rows (y, z) of faces, each padded
 // by 4 positions before and 4 after.
 template <typename T, int LIM>
-__global__ __launch_bounds__(256) void field_lanes_kernel(FieldArgs<T> a) {
+__global__ __launch_bounds__(256) void field_lanes_kernel(FieldLaunch<T> FL) {
   constexpr int D = 0;
+  const BoxDesc* d;
+  int lw;
+  if (!work_item<K_FIELD_X>(FL.wl, d, lw)) return;
+  const FieldArgs<T> a = field_view<T, K_FIELD_X>(FL, *d);
   const Geo& g = a.g;
   const int nx = g.n[0];
   const bool outx = g.bc[0] == 1;
@@ -843,7 +924,7 @@ __global__ __launch_bounds__(256) void field_lanes_kernel(FieldArgs<T> a) {
   const int ry = g.n[1] + g.bc[1];
   const int rz = g.n[2] + g.bc[2];
   const long long nrows = (long long)ry * rz;
-  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const long long wave = lw;
   const int lane = threadIdx.x & 63;
   const long long r0 = wave * a.rows_per_wave;
   if (r0 >= nrows) return;  // whole wave exits together
@@ -917,94 +998,80 @@ __global__ __launch_bounds__(256) void field_lanes_kernel(FieldArgs<T> a) {
 
 // ------------------------------------------------------------ CFL + state check
 template <typename T>
-struct CheckArgs {
+struct CheckLaunch {
   const T* u[5];
   const T* b[3];
-  Geo g;
   double gamma;
+  WorkList wl;
   Scalars* sc;
 };
 
-__device__ __forceinline__ double fast_speed64(const double* u, const double* b, int d, double gamma, double p,
-                                               double b2) {
-  const double rho = u[0];
-  const double a2 = gamma * p / rho;
-  const double q = a2 + b2 / rho;
-  const double disc = q * q - 4.0 * a2 * b[d] * b[d] / rho;
-  return sqrt(0.5 * (q + sqrt(disc < 0.0 ? 0.0 : disc)));
-}
-
-// Eq. (14)-(15): max over cells and active axes of (|v_d| + c_F,d)/h_d in FP64,
-// plus the state check (rho > 0, p > 0, every value finite).
+// Eq. (14)-(15) on the stored state: the CFL speed of every cell (the same
+// function, hence bitwise the same value, as the reduction fused into the
+// last sweep of a step) and the state check (rho > 0, p > 0, every value
+// finite).  A wave covers 64 * par consecutive cells of its box.
 template <typename T>
-__global__ __launch_bounds__(256) void check_cfl_kernel(CheckArgs<T> a) {
-  const Geo& g = a.g;
+__global__ __launch_bounds__(256) void check_cfl_kernel(CheckLaunch<T> L) {
+  const BoxDesc* d;
+  int lw;
+  if (!work_item<K_CHECK>(L.wl, d, lw)) return;
+  const Geo g = d->g;
+  const long long off = d->off;
   const long long ncell = (long long)g.n[0] * g.n[1] * g.n[2];
+  const long long c0 = (long long)lw * 64 * d->par[K_CHECK];
+  const long long c1 = min(ncell, c0 + 64ll * d->par[K_CHECK]);
   double cmax = 0.0;
   int bad = 0;
-  for (long long cidx = (long long)blockIdx.x * blockDim.x + threadIdx.x; cidx < ncell;
-       cidx += (long long)gridDim.x * blockDim.x) {
+  for (long long cidx = c0 + (threadIdx.x & 63); cidx < c1; cidx += 64) {
     const int i = (int)(cidx % g.n[0]);
     const long long r = cidx / g.n[0];
     const int j = (int)(r % g.n[1]);
     const int k = (int)(r / g.n[1]);
-    const long long s = (long long)i * g.st[0] + (long long)j * g.st[1] + (long long)k * g.st[2];
-    double u[5], b[3];
+    const long long s = off + (long long)i * g.st[0] + (long long)j * g.st[1] + (long long)k * g.st[2];
+    T u[5], b[3];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      u[f] = (double)a.u[f][s];
-      if (!isfinite(u[f])) bad = 1;
-    }
+    for (int f = 0; f < 5; ++f) u[f] = L.u[f][s];
     const long long sx = s + (long long)(map_face(i + 1, g.n[0], g.bc[0]) - i) * g.st[0];
     const long long sy = s + (long long)(map_face(j + 1, g.n[1], g.bc[1]) - j) * g.st[1];
     const long long sz = s + (long long)(map_face(k + 1, g.n[2], g.bc[2]) - k) * g.st[2];
-    b[0] = 0.5 * ((double)a.b[0][s] + (double)a.b[0][sx]);
-    b[1] = 0.5 * ((double)a.b[1][s] + (double)a.b[1][sy]);
-    b[2] = 0.5 * ((double)a.b[2][s] + (double)a.b[2][sz]);
+    b[0] = T(0.5) * (L.b[0][s] + L.b[0][sx]);
+    b[1] = T(0.5) * (L.b[1][s] + L.b[1][sy]);
+    b[2] = T(0.5) * (L.b[2][s] + L.b[2][sz]);
     if (!isfinite(b[0]) || !isfinite(b[1]) || !isfinite(b[2])) bad = 1;
-    const double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-    const double m2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
-    const double p = (a.gamma - 1.0) * (u[4] - 0.5 * m2 / u[0] - 0.5 * b2);
-    if (!(u[0] > 0.0) || !(p > 0.0)) bad = 1;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      if (g.n[d] > 1) {
-        const double cf = fast_speed64(u, b, d, a.gamma, p, b2);
-        const double sp = (fabs(u[1 + d] / u[0]) + cf) / g.h[d];
-        if (!isfinite(sp)) bad = 1;
-        cmax = fmax(cmax, sp);
-      }
-    }
+    cmax = fmax(cmax, cell_cfl_speed<T>(u, b, L.gamma, g, bad));
   }
-  // wavefront reduction (64 lanes), then one atomic per wave
-  unsigned long long bits = __double_as_longlong(cmax);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const unsigned long long o = __shfl_xor(bits, off, 64);
-    bits = o > bits ? o : bits;
-    bad |= __shfl_xor(bad, off, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    atomicMax(&a.sc->cmax_bits, bits);
-    if (bad) atomicOr(&a.sc->status, 1);
-  }
+  publish_cfl(cmax, bad, L.sc + d->slot);
 }
 
-__global__ void reset_cmax_kernel(Scalars* sc) { sc->cmax_bits = 0ull; }
+// Per-box step scalars; one thread per box of the table.
+__global__ void reset_cmax_kernel(const BoxDesc* boxes, int nb, Scalars* sc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) sc[boxes[i].slot].cmax_bits = 0ull;
+}
 
-// dt = k / cmax (Eq. 14); a bad reduction marks the state.
-__global__ void finalize_dt_kernel(Scalars* sc, double cfl) {
-  const double cmax = __longlong_as_double((long long)sc->cmax_bits);
-  if (!(cmax > 0.0) || !isfinite(cmax)) {
-    sc->status |= 1;
-    sc->dt = 0.0;
+// dt = k / cmax (Eq. 14); a bad reduction marks the state and stops the box.
+__global__ void finalize_dt_kernel(const BoxDesc* boxes, int nb, Scalars* sc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  Scalars* s = sc + boxes[i].slot;
+  const double cmax = __longlong_as_double((long long)s->cmax_bits);
+  if (!(cmax > 0.0) || !isfinite(cmax) || s->status) {
+    s->status |= 1;
+    s->dt = 0.0;
     return;
   }
-  sc->dt = cfl / cmax;
+  s->dt = boxes[i].cfl / cmax;
+}
+
+__global__ void advance_time_kernel(const BoxDesc* boxes, int nb, Scalars* sc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) {
+    Scalars* s = sc + boxes[i].slot;
+    s->t += 2.0 * s->dt;
+  }
 }
 
 __global__ void set_dt_kernel(Scalars* sc, double dt) { sc->dt = dt; }
-__global__ void advance_time_kernel(Scalars* sc) { sc->t += 2.0 * sc->dt; }
 __global__ void set_scalars_kernel(Scalars* sc, double t, int status) {
   sc->t = t;
   sc->status = status;
