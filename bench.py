@@ -338,6 +338,62 @@ def bench_serve(args, torch, fish, fi):
     print(json.dumps(out), flush=True)
 
 
+def bench_sphere(args, torch, fish, fi):
+    """512^3 stratified sphere: outflow on every face, unsplit gravity and HSE
+    subtraction, FP32 with FP64 pressure recovery, 50 double steps."""
+    n = (args.n if args.n != 256 else 512,) * 3
+    ncell = n[0] * n[1] * n[2]
+    log(f"sphere {n}: generating")
+    t0 = time.perf_counter()
+    st = fi.sphere_state(n, seed=0)
+    log(f"  {time.perf_counter() - t0:.1f} s")
+    box = fish.Box(*n, precision="fp32", bc=(fish.OUTFLOW,) * 3, gravity=True, hse=True, cfl=0.5)
+    box.set_state(st)
+    del st
+    for _ in range(args.warmup):
+        box.strang_step(0.0)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    box.timing_enable(fish.KERNEL_FLUID, max_launches=8 * args.steps)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        box.strang_step(0.0)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches, fluid_ms = box.timing_read()
+    ok = True
+    try:
+        box.cfl_dt()
+    except fish.FishError:
+        ok = False
+    box.close()
+    step_ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps))
+    value = ncell * args.steps / wall
+    fluid_avg_s = fluid_ms / max(1, launches) * 1e-3
+    bytes_fluid = ncell * 14 * 4  # the fluid sweep also reads phi
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{n[0]}^3 stratified sphere rho = 1/(1+(r/0.1)^2) with 1% noise, matching potential "
+                               "and hydrostatic pressure, beta 100, outflow boundaries, unsplit gravity + HSE, "
+                               "gamma 5/3, CFL 0.5, FP32 with FP64 pressure recovery", "cells": ncell},
+        "latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99)},
+        "step_roofline": {"bytes_per_cell": 408, "achieved_GBs": value * 408 / 1e9, "peak_GBs": HBM_PEAK_GBS,
+                          "frac": value * 408 / 1e9 / HBM_PEAK_GBS},
+        "roofline": {"bound": "hbm", "achieved": bytes_fluid / fluid_avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": bytes_fluid / fluid_avg_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "fluid sweep with gravity + HSE", "avg_launch_ms": fluid_avg_s * 1e3,
+                     "launches": launches, "algorithmic_bytes_per_launch": bytes_fluid},
+        "state_ok": ok,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -352,7 +408,7 @@ def main():
                          "box loses positivity after 6 steps, in the oracle as well)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration)")
-    ap.add_argument("--workload", choices=("box", "batch", "serve"), default="box",
+    ap.add_argument("--workload", choices=("box", "batch", "serve", "sphere"), default="box",
                     help="box: the 256^3 box (default); batch: 2048 boxes of uneven size; serve: request loop")
     ap.add_argument("--boxes", type=int, default=2048)
     ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
@@ -389,6 +445,8 @@ def main():
         return bench_batch(args, torch, fish, fi)
     if args.workload == "serve":
         return bench_serve(args, torch, fish, fi)
+    if args.workload == "sphere":
+        return bench_sphere(args, torch, fish, fi)
     n = (args.n,) * 3
     ncell = n[0] * n[1] * n[2]
     cfl = 0.5
