@@ -60,13 +60,14 @@ def load_traffic(name, esize, cells):
     return rec.get("bytes_per_launch")
 
 
-def run_gpu(fish, torch, st, n, precision, steps, warmup, cfl, segment):
+def run_gpu(fish, torch, st, n, precision, steps, warmup, cfl, segment, autotune=True):
     """Time `steps` Strang steps (dt from the device CFL step) in segments of at
     most `segment` steps, each started from the initial state: the state is
     re-uploaded and synchronised before a segment's clock starts and checked
     after it stops, so every timed step advances a physically valid state."""
     box = fish.Box(*n, precision=precision, cfl=cfl)
     box.set_state(st)
+    tuned = box.autotune(reps=3) if autotune else None
     for _ in range(warmup):
         box.strang_step(0.0)
     torch.cuda.synchronize()
@@ -97,7 +98,7 @@ def run_gpu(fish, torch, st, n, precision, steps, warmup, cfl, segment):
     launches, fluid_ms = box.timing_read()
     box.close()
     return {"wall": wall, "step_ms": sorted(step_ms), "fluid_launches": launches, "fluid_ms": fluid_ms,
-            "state_ok": ok}
+            "state_ok": ok, "tuned": tuned}
 
 
 def pct(sorted_vals, q):
@@ -403,6 +404,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default work shapes")
     ap.add_argument("--segment", type=int, default=5,
                     help="timed steps per segment before the initial state is restored (the 256^3 Mach 1, beta 1 "
                          "box loses positivity after 6 steps, in the oracle as well)")
@@ -458,7 +460,8 @@ def main():
     res = {}
     for prec in ("fp32",) + (() if args.no_fp64 else ("fp64",)):
         log(f"GPU {prec}: {args.warmup} warmup + {args.steps} timed steps")
-        res[prec] = run_gpu(fish, torch, st, n, prec, args.steps, args.warmup, cfl, args.segment)
+        res[prec] = run_gpu(fish, torch, st, n, prec, args.steps, args.warmup, cfl, args.segment,
+                            autotune=not args.no_autotune)
         r = res[prec]
         log(f"  {r['wall'] * 1e3 / args.steps:.3f} ms/step, fluid launch avg "
             f"{r['fluid_ms'] / max(1, r['fluid_launches']):.3f} ms, state_ok={r['state_ok']}")
@@ -491,6 +494,7 @@ def main():
             "precision": "FP32 storage and arithmetic, FP64 pressure recovery / CFL reduction",
             "cells": ncell,
             "limiter": "van Leer",
+            "autotuned": r["tuned"],
         },
         "latency_ms": {"p50": pct(r["step_ms"], 50), "p99": pct(r["step_ms"], 99)},
         "step_roofline": {"bytes_per_cell": 384, "achieved_GBs": value * 384 / 1e9, "peak_GBs": HBM_PEAK_GBS,

@@ -333,7 +333,12 @@ class Box:
         """Pick the fastest work shape of every sweep kind; returns {kind: target}."""
         t = (ctypes.c_int32 * 7)()
         self._check(self._lib.fish_autotune(self._h, int(reps), t))
-        return dict(zip(KINDS, list(t)))
+        return _tuned(t)
+
+
+def _tuned(t):
+    """{kind: {"target": shape, "xcd_remap": 0/1}} from the autotuner's output."""
+    return {k: {"target": int(v) & 0xFFFF, "xcd_remap": (int(v) >> 16) & 1} for k, v in zip(KINDS, list(t))}
 
 
 def _diag_dict(out):
@@ -481,7 +486,7 @@ class Batch:
     def autotune(self, reps=3):
         t = (ctypes.c_int32 * 7)()
         self._check(self._lib.fish_batch_autotune(self._h, int(reps), t))
-        return dict(zip(KINDS, list(t)))
+        return _tuned(t)
 
     def sync(self):
         self._check(self._lib.fish_batch_sync(self._h))
@@ -575,7 +580,7 @@ class Server:
         rc = self._lib.fish_batch_autotune(b, int(reps), t)
         if rc != FISH_OK:
             raise FishError(rc, self._lib.fish_batch_last_error(b).decode())
-        return dict(zip(KINDS, list(t)))
+        return _tuned(t)
 
     def use_graph(self, on=True):
         b = self._lib.fish_server_batch(self._h)

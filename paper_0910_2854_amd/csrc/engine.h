@@ -56,6 +56,7 @@ struct EngineConfig {
 // the y/z kinds, cells per lane for the CFL check.
 struct Tuning {
   int target[K_NUM];
+  int remap[K_NUM];   // XCD-aware block order per kind (0/1)
 };
 Tuning default_tuning();
 

@@ -34,6 +34,7 @@ Tuning default_tuning() {
   t.target[K_FLUID_Y] = t.target[K_FLUID_Z] = 64;
   t.target[K_FIELD_Y] = t.target[K_FIELD_Z] = 64;
   t.target[K_CHECK] = 16;
+  for (int k = 0; k < K_NUM; ++k) t.remap[k] = 0;
   return t;
 }
 
@@ -484,6 +485,7 @@ static WorkList make_wl(const Engine* e, int kind) {
   w.boxes = static_cast<const BoxDesc*>(e->table.ptr);
   w.wave_box = static_cast<const int*>(e->lists[kind].ptr);
   w.nwaves = e->nwaves[kind];
+  w.xcd_remap = e->tuning.remap[kind];
   return w;
 }
 
@@ -811,18 +813,22 @@ int Engine::autotune(int reps, int* chosen) {
     const int d = op ? kind - K_FIELD_X : kind - K_FLUID_X;
     float best = 1e30f;
     int best_t = tuning.target[kind];
-    int last_par_sig = -1;
-    for (int ci = 0; ci < ncand && !rc; ++ci) {
+    int best_r = tuning.remap[kind];
+    std::vector<int> seen;
+    for (int cj = 0; cj < 2 * ncand && !rc; ++cj) {
+      const int ci = cj >> 1;
       tuning.target[kind] = cand[ci];
-      // skip candidates that give every box the same shape as the previous one
+      tuning.remap[kind] = cj & 1;
+      // skip candidates that give every box a shape already timed
       int sig = 0;
       for (int s : table_slots) {
         int par = 0;
         (void)kind_waves(boxes[s], kind, cand[ci], &par);
         sig = sig * 31 + par;
       }
-      if (sig == last_par_sig) continue;
-      last_par_sig = sig;
+      sig = sig * 2 + (cj & 1);
+      if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
+      seen.push_back(sig);
       if ((rc = build_lists())) break;
       int saved[8];
       std::memcpy(saved, cur, sizeof cur);
@@ -845,10 +851,12 @@ int Engine::autotune(int reps, int* chosen) {
       if (ms < best) {
         best = ms;
         best_t = cand[ci];
+        best_r = cj & 1;
       }
     }
     tuning.target[kind] = best_t;
-    if (chosen) chosen[kind] = best_t;
+    tuning.remap[kind] = best_r;
+    if (chosen) chosen[kind] = best_t | (best_r << 16);
     if (rc) break;
   }
   timing_mask = saved_mask;

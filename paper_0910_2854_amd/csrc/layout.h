@@ -41,6 +41,7 @@ struct WorkList {
   const BoxDesc* boxes;
   const int* wave_box;  // table index of the box of every wave
   int nwaves;
+  int xcd_remap;        // 1: consecutive blocks of the list run on one XCD (see work_item)
 };
 
 }  // namespace fish

@@ -29,9 +29,24 @@ namespace fish {
 
 // The wave's box and its wave index within the box; false past the list
 // (the whole wave exits together).
+// Blocks are dealt round-robin to the 8 XCDs, each with its own L2.  With
+// xcd_remap the list's block order is re-dealt so that the blocks an XCD runs
+// are consecutive in the list (neighbouring pencils and rows, whose shared
+// halo rows then hit in that XCD's L2); the full rounds of 8 are permuted, a
+// ragged tail keeps its order.
+__device__ __forceinline__ int list_block(int xcd_remap) {
+  int b = (int)blockIdx.x;
+  if (xcd_remap) {
+    const int q = (int)gridDim.x >> 3;
+    if (b < (q << 3)) b = (b & 7) * q + (b >> 3);
+  }
+  return b;
+}
+
 template <int KIND>
 __device__ __forceinline__ bool work_item(const WorkList& wl, const BoxDesc*& d, int& lw) {
-  const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  const int wave =
+      __builtin_amdgcn_readfirstlane((int)((list_block(wl.xcd_remap) * blockDim.x + threadIdx.x) >> 6));
   if (wave >= wl.nwaves) return false;
   d = wl.boxes + wl.wave_box[wave];
   lw = wave - d->wave0[KIND];
