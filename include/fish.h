@@ -273,10 +273,12 @@ int fish_batch_timing_read(fish_batch* b, int* launches, double* total_ms);
  *
  * Requests (a box, its state and a number of double steps) wait in a FIFO
  * queue.  Each fish_server_pump call
- *   1. admits queued requests in arrival order while the head fits in the
- *      batch's pool (the HBM budget; a request never overtakes the head),
- *   2. advances every resident box by k = min(chunk, fewest steps left) double
- *      steps in the same launches (each box with its own CFL step), and
+ *   1. enqueues k = min(chunk, fewest steps left) double steps of every
+ *      resident box in the same launches (each box with its own CFL step),
+ *   2. while they run, admits queued requests in arrival order while the head
+ *      fits in the batch's pool (the HBM budget; a request never overtakes the
+ *      head); their host repacking and copies overlap the steps, and they
+ *      take their first step in the next call, and
  *   3. retires the boxes that are done: their state is written to the
  *      request's output arrays and their pool range is freed.
  * A request's result is the same as stepping its box alone (bitwise).

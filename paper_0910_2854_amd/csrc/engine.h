@@ -93,8 +93,17 @@ class Engine {
   bool graph_ok = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  std::vector<std::pair<hipGraph_t, hipGraphExec_t>> retired_graphs;
 
   bool last_fluid_cfl = false;
+
+  // host transfers: pinned staging pair on the copy stream
+  static constexpr size_t kStageBytes = 32u << 20;
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t copy_ev = nullptr, compute_ev = nullptr;
+  hipEvent_t stage_ev[2] = {nullptr, nullptr};
+  void* stage[2] = {nullptr, nullptr};
+  size_t stage_bytes = 0;
 
   // measurement hook
   int timing_mask = 0;
@@ -131,12 +140,14 @@ class Engine {
   int set_graph(bool on);
 
  private:
+  int ensure_stage(size_t bytes);
   int dev_alloc(DeviceBuf& b, size_t bytes);
   void dev_free(DeviceBuf& b);
   int launch_check();
   int run_sub(int op, int d);
   int enqueue_step_cfl();                   // the launches of one CFL-stepped double step
   void invalidate_graph();
+  void drop_retired_graphs();
   int build_lists();
   template <typename T>
   int sub_operator(int op, int d);

@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
+#include <thread>
 
 namespace fish {
 
@@ -120,6 +122,10 @@ int Engine::init(const EngineConfig& c, long long cap_elems, int max_boxes) {
   if (!rc) rc = dev_alloc(partial, (size_t)npartial * 10 * sizeof(double));
   if (!rc) rc = dev_alloc(diag_out, 16 * sizeof(double));
   if (rc) return rc;
+  HIP_TRY(hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&copy_ev, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&compute_ev, hipEventDisableTiming));
+  for (int b = 0; b < 2; ++b) HIP_TRY(hipEventCreateWithFlags(&stage_ev[b], hipEventDisableTiming));
   boxes.assign(max_boxes, HostBox());
   free_list.clear();
   free_list[0] = cap;
@@ -136,7 +142,21 @@ void Engine::release() {
   live = false;
   (void)hipSetDevice(cfg.device);
   (void)hipStreamSynchronize(cfg.stream);
+  if (copy_stream) (void)hipStreamSynchronize(copy_stream);
   invalidate_graph();
+  drop_retired_graphs();
+  for (int b = 0; b < 2; ++b) {
+    if (stage[b]) (void)hipHostFree(stage[b]);
+    stage[b] = nullptr;
+    if (stage_ev[b]) (void)hipEventDestroy(stage_ev[b]);
+    stage_ev[b] = nullptr;
+  }
+  stage_bytes = 0;
+  if (copy_ev) (void)hipEventDestroy(copy_ev);
+  if (compute_ev) (void)hipEventDestroy(compute_ev);
+  copy_ev = compute_ev = nullptr;
+  if (copy_stream) (void)hipStreamDestroy(copy_stream);
+  copy_stream = nullptr;
   for (auto e : ev_start) (void)hipEventDestroy(e);
   for (auto e : ev_stop) (void)hipEventDestroy(e);
   ev_start.clear();
@@ -151,12 +171,21 @@ void Engine::release() {
   dev_free(diag_out);
 }
 
+// A graph may still be executing when the set of boxes changes: it is only
+// destroyed after the next synchronisation of the stream.
 void Engine::invalidate_graph() {
-  if (gexec) (void)hipGraphExecDestroy(gexec);
-  if (graph) (void)hipGraphDestroy(graph);
+  if (gexec || graph) retired_graphs.push_back({graph, gexec});
   gexec = nullptr;
   graph = nullptr;
   graph_ok = false;
+}
+
+void Engine::drop_retired_graphs() {
+  for (auto& g : retired_graphs) {
+    if (g.second) (void)hipGraphExecDestroy(g.second);
+    if (g.first) (void)hipGraphDestroy(g.first);
+  }
+  retired_graphs.clear();
 }
 
 // ------------------------------------------------------------ boxes
@@ -234,6 +263,7 @@ int Engine::remove_box(int slot) {
   int rc = set_device();
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(cfg.stream));  // no launch in flight reads its range
+  drop_retired_graphs();
   HostBox& b = boxes[slot];
   long long off = b.off, len = b.reserved;
   // return the range and merge with its neighbours
@@ -258,79 +288,156 @@ int Engine::remove_box(int slot) {
   return 0;
 }
 
-// Host-side repacking between the interface layout and the device layout.
-// Face array `a` (0 = x) along its own normal: the interface carries n+1
-// faces; the device stores n (periodic) or n+1 (outflow).
-template <typename T>
-static void pack_cell(const HostBox& c, const double* src, std::vector<T>& dst) {
-  const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
-  for (int k = 0; k < nz; ++k)
-    for (int j = 0; j < ny; ++j)
-      for (int i = 0; i < nx; ++i)
-        dst[i + c.st[1] * j + c.st[2] * k] = (T)src[(size_t)i + (size_t)nx * (j + (size_t)ny * k)];
+// ------------------------------------------------------------ host transfers
+// Host arrays (the interface layout, FP64) are repacked into the device layout
+// and precision in pinned staging buffers, several threads at a time, and
+// cross PCIe on the copy stream: two staging buffers alternate, so the host
+// packs one chunk (whole z-planes of the device layout) while the previous
+// one is copied.  The compute stream waits for an upload through an event;
+// a download waits for the compute stream the same way.
+
+// Run f(a, b) over [0, n) split across up to 16 threads.
+static void parallel_for(long long n, const std::function<void(long long, long long)>& f) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const long long nt = std::min<long long>(std::min<long long>(hw, 16), n);
+  if (nt <= 1 || n < 8) {
+    f(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve((size_t)nt);
+  for (long long t = 0; t < nt; ++t) th.emplace_back(f, n * t / nt, n * (t + 1) / nt);
+  for (auto& x : th) x.join();
 }
 
-template <typename T>
-static void pack_face(const HostBox& c, int a, const double* src, std::vector<T>& dst) {
-  int m[3] = {c.n[0], c.n[1], c.n[2]};  // input extents
-  m[a] += 1;
-  int keep[3] = {c.n[0], c.n[1], c.n[2]};  // stored faces
-  keep[a] += c.o[a];
-  for (int k = 0; k < keep[2]; ++k)
-    for (int j = 0; j < keep[1]; ++j)
-      for (int i = 0; i < keep[0]; ++i)
-        dst[i + c.st[1] * j + c.st[2] * k] = (T)src[(size_t)i + (size_t)m[0] * (j + (size_t)m[1] * k)];
+// Array a of a box: 0-4 cell fields, 5-7 face fields along x, y, z, 8 phi.
+// Interface extents m (n, with n+1 along its own normal for a face array);
+// stored extents keep (n, with n+o along its own normal); device extents
+// ext = n + o on every axis.
+struct ArrayShape {
+  int m[3], keep[3], ext[3];
+  long long st1, st2;
+};
+
+static ArrayShape array_shape(const HostBox& c, int a) {
+  ArrayShape s;
+  for (int x = 0; x < 3; ++x) {
+    s.m[x] = c.n[x];
+    s.keep[x] = c.n[x];
+    s.ext[x] = c.n[x] + c.o[x];
+  }
+  if (a >= 5 && a <= 7) {
+    const int ax = a - 5;
+    s.m[ax] += 1;
+    s.keep[ax] += c.o[ax];
+  }
+  s.st1 = c.st[1];
+  s.st2 = c.st[2];
+  return s;
 }
 
+// Device planes [k0, k1) of array a from the interface array src into dst
+// (zero outside the stored region).
 template <typename T>
-static void unpack_cell(const HostBox& c, const std::vector<T>& src, double* dst, size_t field_off) {
-  const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
-  for (int k = 0; k < nz; ++k)
-    for (int j = 0; j < ny; ++j)
-      for (int i = 0; i < nx; ++i)
-        dst[field_off + (size_t)i + (size_t)nx * (j + (size_t)ny * k)] = (double)src[i + c.st[1] * j + c.st[2] * k];
-}
-
-template <typename T>
-static void unpack_face(const HostBox& c, int a, const std::vector<T>& src, double* dst) {
-  int m[3] = {c.n[0], c.n[1], c.n[2]};
-  m[a] += 1;
-  for (int k = 0; k < m[2]; ++k)
-    for (int j = 0; j < m[1]; ++j)
-      for (int i = 0; i < m[0]; ++i) {
-        int q[3] = {i, j, k};
-        if (c.bc[a] == 0 && q[a] == c.n[a]) q[a] = 0;  // face n is face 0
-        dst[(size_t)i + (size_t)m[0] * (j + (size_t)m[1] * k)] = (double)src[q[0] + c.st[1] * q[1] + c.st[2] * q[2]];
+static void pack_planes(const HostBox& c, int a, const double* src, T* dst, int k0, int k1) {
+  const ArrayShape s = array_shape(c, a);
+  const long long rows = (long long)(k1 - k0) * s.ext[1];
+  parallel_for(rows, [&](long long r0, long long r1) {
+    for (long long r = r0; r < r1; ++r) {
+      const int k = k0 + (int)(r / s.ext[1]);
+      const int j = (int)(r % s.ext[1]);
+      T* d = dst + (long long)(k - k0) * s.st2 + (long long)j * s.st1;
+      if (k >= s.keep[2] || j >= s.keep[1]) {
+        for (int i = 0; i < s.ext[0]; ++i) d[i] = T(0);
+        continue;
       }
+      const double* q = src + (size_t)s.m[0] * ((size_t)j + (size_t)s.m[1] * k);
+      for (int i = 0; i < s.keep[0]; ++i) d[i] = (T)q[i];
+      for (int i = s.keep[0]; i < s.ext[0]; ++i) d[i] = T(0);
+    }
+  });
+}
+
+// Interface planes of array a whose device plane lies in [k0, k1), from the
+// device planes in src.  On a periodic axis face n is written equal to face 0.
+template <typename T>
+static void unpack_planes(const HostBox& c, int a, const T* src, double* dst, int k0, int k1) {
+  const ArrayShape s = array_shape(c, a);
+  const int ax = (a >= 5 && a <= 7) ? a - 5 : -1;
+  // interface planes to fill: k in [k0, k1) within m[2], plus plane n of a
+  // periodic z-face array when device plane 0 is in the chunk
+  std::vector<std::pair<int, int>> planes;  // (interface k, device k)
+  for (int k = k0; k < k1 && k < s.m[2]; ++k) planes.push_back({k, k});
+  if (ax == 2 && c.bc[2] == 0 && k0 == 0) planes.push_back({c.n[2], 0});
+  if (ax == 2 && c.bc[2] == 0) {
+    // interface plane n maps to device plane 0, never to device plane n
+    planes.erase(std::remove_if(planes.begin(), planes.end(),
+                                [&](const std::pair<int, int>& p) { return p.first == c.n[2] && p.second != 0; }),
+                 planes.end());
+  }
+  const long long rows = (long long)planes.size() * s.m[1];
+  parallel_for(rows, [&](long long r0, long long r1) {
+    for (long long r = r0; r < r1; ++r) {
+      const auto& pk = planes[(size_t)(r / s.m[1])];
+      int j = (int)(r % s.m[1]);
+      double* d = dst + (size_t)s.m[0] * ((size_t)j + (size_t)s.m[1] * pk.first);
+      if (ax == 1 && c.bc[1] == 0 && j == c.n[1]) j = 0;  // face n is face 0
+      const T* q = src + (long long)(pk.second - k0) * s.st2 + (long long)j * s.st1;
+      if (ax == 0 && c.bc[0] == 0) {
+        for (int i = 0; i < c.n[0]; ++i) d[i] = (double)q[i];
+        d[c.n[0]] = (double)q[0];
+      } else {
+        for (int i = 0; i < s.m[0]; ++i) d[i] = (double)q[i];
+      }
+    }
+  });
+}
+
+int Engine::ensure_stage(size_t bytes) {
+  bytes = std::max(bytes, kStageBytes);
+  if (stage_bytes >= bytes) return 0;
+  for (int b = 0; b < 2; ++b) {
+    if (stage[b]) (void)hipHostFree(stage[b]);
+    stage[b] = nullptr;
+  }
+  stage_bytes = 0;
+  for (int b = 0; b < 2; ++b) HIP_TRY(hipHostMalloc(&stage[b], bytes, hipHostMallocDefault));
+  stage_bytes = bytes;
+  return 0;
 }
 
 template <typename T>
 int Engine::upload_t(int slot, const double* cell5, const double* bx, const double* by, const double* bz,
                      const double* phi_in) {
   const HostBox& c = boxes[slot];
-  std::vector<T> h((size_t)c.nelem, T(0));
   const size_t nc = (size_t)c.n[0] * c.n[1] * c.n[2];
-  const size_t bytes = (size_t)c.nelem * sizeof(T);
-  for (int f = 0; f < 5; ++f) {
-    std::fill(h.begin(), h.end(), T(0));
-    pack_cell<T>(c, cell5 + f * nc, h);
-    HIP_TRY(hipMemcpyAsync((T*)pool[cur[f]][f].ptr + c.off, h.data(), bytes, hipMemcpyHostToDevice, cfg.stream));
-    HIP_TRY(hipStreamSynchronize(cfg.stream));
+  const size_t plane = (size_t)c.st[2] * sizeof(T);
+  int rc = ensure_stage(plane);
+  if (rc) return rc;
+  const int ppc = (int)std::max<size_t>(1, stage_bytes / plane);
+  const int nz = c.n[2] + c.o[2];
+  if (c.have_state) {
+    // the box's range may still be read by launches already enqueued
+    HIP_TRY(hipEventRecord(compute_ev, cfg.stream));
+    HIP_TRY(hipStreamWaitEvent(copy_stream, compute_ev, 0));
   }
-  const double* bsrc[3] = {bx, by, bz};
-  for (int a = 0; a < 3; ++a) {
-    std::fill(h.begin(), h.end(), T(0));
-    pack_face<T>(c, a, bsrc[a], h);
-    HIP_TRY(hipMemcpyAsync((T*)pool[cur[5 + a]][5 + a].ptr + c.off, h.data(), bytes, hipMemcpyHostToDevice,
-                           cfg.stream));
-    HIP_TRY(hipStreamSynchronize(cfg.stream));
+  int idx = 0;
+  for (int a = 0; a < 9; ++a) {
+    if (a == 8 && !cfg.gravity) break;
+    const double* src = a < 5 ? cell5 + a * nc : a == 5 ? bx : a == 6 ? by : a == 7 ? bz : phi_in;
+    T* dev = (a < 8 ? (T*)pool[cur[a]][a].ptr : (T*)phi.ptr) + c.off;
+    for (int k0 = 0; k0 < nz; k0 += ppc) {
+      const int k1 = std::min(nz, k0 + ppc);
+      HIP_TRY(hipEventSynchronize(stage_ev[idx]));  // the buffer's previous copy is done
+      pack_planes<T>(c, a, src, (T*)stage[idx], k0, k1);
+      HIP_TRY(hipMemcpyAsync(dev + (long long)k0 * c.st[2], stage[idx], (size_t)(k1 - k0) * plane,
+                             hipMemcpyHostToDevice, copy_stream));
+      HIP_TRY(hipEventRecord(stage_ev[idx], copy_stream));
+      idx ^= 1;
+    }
   }
-  if (cfg.gravity) {
-    std::fill(h.begin(), h.end(), T(0));
-    pack_cell<T>(c, phi_in, h);
-    HIP_TRY(hipMemcpyAsync((T*)phi.ptr + c.off, h.data(), bytes, hipMemcpyHostToDevice, cfg.stream));
-    HIP_TRY(hipStreamSynchronize(cfg.stream));
-  }
+  HIP_TRY(hipEventRecord(copy_ev, copy_stream));
+  HIP_TRY(hipStreamWaitEvent(cfg.stream, copy_ev, 0));
   return 0;
 }
 
@@ -339,7 +446,6 @@ int Engine::upload(int slot, const double* cell5, const double* bx, const double
   if (slot < 0 || slot >= (int)boxes.size() || !boxes[slot].used) return fail(1, "no such box");
   int rc = set_device();
   if (rc) return rc;
-  HIP_TRY(hipStreamSynchronize(cfg.stream));
   rc = esize == 8 ? upload_t<double>(slot, cell5, bx, by, bz, phi_in) : upload_t<float>(slot, cell5, bx, by, bz, phi_in);
   if (rc) return rc;
   hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(1), 0, cfg.stream, (Scalars*)scal.ptr + slot, 0.0, 0);
@@ -359,23 +465,46 @@ int Engine::upload(int slot, const double* cell5, const double* bx, const double
 template <typename T>
 int Engine::download_t(int slot, double* cell5, double* bx, double* by, double* bz) {
   const HostBox& c = boxes[slot];
-  std::vector<T> h((size_t)c.nelem);
   const size_t nc = (size_t)c.n[0] * c.n[1] * c.n[2];
-  const size_t bytes = (size_t)c.nelem * sizeof(T);
-  if (cell5)
-    for (int f = 0; f < 5; ++f) {
-      HIP_TRY(hipMemcpyAsync(h.data(), (T*)pool[cur[f]][f].ptr + c.off, bytes, hipMemcpyDeviceToHost, cfg.stream));
-      HIP_TRY(hipStreamSynchronize(cfg.stream));
-      unpack_cell<T>(c, h, cell5, f * nc);
+  const size_t plane = (size_t)c.st[2] * sizeof(T);
+  int rc = ensure_stage(plane);
+  if (rc) return rc;
+  const int ppc = (int)std::max<size_t>(1, stage_bytes / plane);
+  const int nz = c.n[2] + c.o[2];
+  HIP_TRY(hipEventRecord(compute_ev, cfg.stream));
+  HIP_TRY(hipStreamWaitEvent(copy_stream, compute_ev, 0));
+  // chunks in order; chunk i is unpacked while chunk i+1 is copied
+  struct Pending {
+    int a, k0, k1, idx;
+    double* dst;
+  };
+  std::vector<Pending> pend;
+  int idx = 0;
+  auto drain = [&](const Pending& q) -> int {
+    HIP_TRY(hipEventSynchronize(stage_ev[q.idx]));
+    unpack_planes<T>(c, q.a, (const T*)stage[q.idx], q.dst, q.k0, q.k1);
+    return 0;
+  };
+  for (int a = 0; a < 8; ++a) {
+    double* dst = a < 5 ? (cell5 ? cell5 + a * nc : nullptr) : a == 5 ? bx : a == 6 ? by : bz;
+    if (!dst) continue;
+    const T* dev = (const T*)pool[cur[a]][a].ptr + c.off;
+    for (int k0 = 0; k0 < nz; k0 += ppc) {
+      const int k1 = std::min(nz, k0 + ppc);
+      // the buffer is free once its previous chunk has been unpacked
+      if (!pend.empty() && pend.front().idx == idx) {
+        if ((rc = drain(pend.front()))) return rc;
+        pend.erase(pend.begin());
+      }
+      HIP_TRY(hipMemcpyAsync(stage[idx], dev + (long long)k0 * c.st[2], (size_t)(k1 - k0) * plane,
+                             hipMemcpyDeviceToHost, copy_stream));
+      HIP_TRY(hipEventRecord(stage_ev[idx], copy_stream));
+      pend.push_back({a, k0, k1, idx, dst});
+      idx ^= 1;
     }
-  double* bdst[3] = {bx, by, bz};
-  for (int a = 0; a < 3; ++a) {
-    if (!bdst[a]) continue;
-    HIP_TRY(hipMemcpyAsync(h.data(), (T*)pool[cur[5 + a]][5 + a].ptr + c.off, bytes, hipMemcpyDeviceToHost,
-                           cfg.stream));
-    HIP_TRY(hipStreamSynchronize(cfg.stream));
-    unpack_face<T>(c, a, h, bdst[a]);
   }
+  for (const auto& q : pend)
+    if ((rc = drain(q))) return rc;
   return 0;
 }
 
@@ -463,6 +592,7 @@ int Engine::build_lists() {
   int rc = set_device();
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(cfg.stream));  // nothing in flight reads the old lists
+  drop_retired_graphs();
   if (nb > 0) HIP_TRY(hipMemcpy(table.ptr, desc.data(), sizeof(BoxDesc) * nb, hipMemcpyHostToDevice));
   for (int k = 0; k < K_NUM; ++k) {
     const size_t bytes = list[k].size() * sizeof(int);

@@ -90,7 +90,18 @@ int fish_server_submit(fish_server* s, const fish_request* r) {
 int fish_server_pump(fish_server* s, int64_t* done_tags, int32_t* done_status, int max_done, int* ndone) {
   if (!s || !ndone || (max_done > 0 && !done_tags)) return s ? sfail(s, FISH_ERR_ARG, "bad output") : FISH_ERR_ARG;
   *ndone = 0;
-  // admission in arrival order while the head fits (no overtaking)
+  // 1. the next chunk of steps of every resident box, enqueued first so that
+  //    the host work of the admissions below overlaps it; no box overshoots
+  int k = 0;
+  if (!s->resident.empty()) {
+    k = s->chunk;
+    for (const auto& x : s->resident) k = std::min(k, x.left);
+    int rc = fish_batch_step(s->batch, k);
+    if (rc) return sfail(s, rc, fish_batch_last_error(s->batch));
+  }
+  const size_t stepped = s->resident.size();
+  // 2. admission in arrival order while the head fits (no overtaking); the
+  //    new boxes take no step of this chunk
   while (!s->queue.empty()) {
     const fish_request& r = s->queue.front();
     int id = -1;
@@ -108,18 +119,13 @@ int fish_server_pump(fish_server* s, int64_t* done_tags, int32_t* done_status, i
     s->resident.push_back({r, id, r.nsteps});
     s->queue.pop_front();
   }
-  if (s->resident.empty()) return FISH_OK;
-  // advance every resident box by the same number of steps: no box overshoots
-  int k = s->chunk;
-  for (const auto& x : s->resident) k = std::min(k, x.left);
-  int rc = fish_batch_step(s->batch, k);
-  if (rc) return sfail(s, rc, fish_batch_last_error(s->batch));
-  for (auto& x : s->resident) {
+  for (size_t i = 0; i < stepped; ++i) {
+    auto& x = s->resident[i];
     x.left -= k;
     s->cell_steps += (long long)k * x.req.box.nx * x.req.box.ny * x.req.box.nz;
   }
   s->steps_done += k;
-  // retire finished boxes
+  // 3. retire finished boxes (their downloads wait for the chunk)
   std::vector<fish_server::Resident> keep;
   keep.reserve(s->resident.size());
   for (auto& x : s->resident) {
@@ -134,7 +140,8 @@ int fish_server_pump(fish_server* s, int64_t* done_tags, int32_t* done_status, i
     double t = 0.0;
     int st = fish_batch_get(s->batch, x.id, x.req.out_cell5, x.req.out_bx, x.req.out_by, x.req.out_bz, &t);
     if (st != FISH_OK && st != FISH_ERR_STATE) return sfail(s, st, fish_batch_last_error(s->batch));
-    if ((rc = fish_batch_remove(s->batch, x.id))) return sfail(s, rc, fish_batch_last_error(s->batch));
+    int rc = fish_batch_remove(s->batch, x.id);
+    if (rc) return sfail(s, rc, fish_batch_last_error(s->batch));
     done_tags[*ndone] = x.req.tag;
     if (done_status) done_status[*ndone] = st;
     ++*ndone;
