@@ -161,9 +161,11 @@ enum {
  * fastest; the state is unchanged.  Shapes: stream positions per wavefront
  * for the x kinds (whole rows), segment length along the sweep for the y/z
  * kinds, each with the plain or the XCD-grouped block order (consecutive
- * blocks of a launch on one XCD, sharing its L2).  targets_out (may be NULL)
- * receives FISH_NUM_KINDS chosen values: the shape in bits 0-15, the block
- * order (1 = XCD-grouped) in bit 16.
+ * blocks of a launch on one XCD, sharing its L2), and for the y/z kinds with
+ * contiguous pencils per wave or the four waves of a block on four
+ * consecutive rows.  targets_out (may be NULL) receives FISH_NUM_KINDS chosen
+ * values: the shape in bits 0-15, the block order (1 = XCD-grouped) in bit
+ * 16, the row grouping in bit 17.
  * Results do not depend on the shapes (each cell is computed by the same
  * operations whatever wave computes it).  Synchronises the stream. */
 int fish_autotune(fish_ctx* ctx, int reps, int32_t* targets_out);

@@ -337,8 +337,9 @@ class Box:
 
 
 def _tuned(t):
-    """{kind: {"target": shape, "xcd_remap": 0/1}} from the autotuner's output."""
-    return {k: {"target": int(v) & 0xFFFF, "xcd_remap": (int(v) >> 16) & 1} for k, v in zip(KINDS, list(t))}
+    """{kind: {"target": shape, "xcd_remap": 0/1, "row_groups": 0/1}} from the autotuner's output."""
+    return {k: {"target": int(v) & 0xFFFF, "xcd_remap": (int(v) >> 16) & 1, "row_groups": (int(v) >> 17) & 1}
+            for k, v in zip(KINDS, list(t))}
 
 
 def _diag_dict(out):

@@ -57,6 +57,7 @@ struct EngineConfig {
 struct Tuning {
   int target[K_NUM];
   int remap[K_NUM];   // XCD-aware block order per kind (0/1)
+  int groups[K_NUM];  // y/z kinds: waves of a block on consecutive rows (0/1)
 };
 Tuning default_tuning();
 

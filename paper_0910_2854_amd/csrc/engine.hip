@@ -36,7 +36,7 @@ Tuning default_tuning() {
   t.target[K_FLUID_Y] = t.target[K_FLUID_Z] = 64;
   t.target[K_FIELD_Y] = t.target[K_FIELD_Z] = 64;
   t.target[K_CHECK] = 16;
-  for (int k = 0; k < K_NUM; ++k) t.remap[k] = 0;
+  for (int k = 0; k < K_NUM; ++k) t.remap[k] = t.groups[k] = 0;
   return t;
 }
 
@@ -525,7 +525,13 @@ int Engine::read_scalars(int slot, Scalars* out) {
 static long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 
 // Waves of one box in the list of one kind, and the per-box parameter.
-static long long kind_waves(const HostBox& b, int kind, int target, int* par) {
+// Pencil waves of one segment of a y/z kind (strided_map's two orders).
+static long long strided_waves(long long nA, long long nO, int groups) {
+  if (groups && nA >= 64) return ceil_div(nA, 64) * ceil_div(nO, 4) * 4;
+  return ceil_div(nA * nO, 64);
+}
+
+static long long kind_waves(const HostBox& b, int kind, int target, int groups, int* par) {
   switch (kind) {
     case K_FLUID_X: {
       const int rpw = std::max(1, target / (b.n[0] + 6));
@@ -542,14 +548,14 @@ static long long kind_waves(const HostBox& b, int kind, int target, int* par) {
       const int D = kind - K_FLUID_X;
       const int seg = std::max(1, std::min(target, b.n[D]));
       *par = seg;
-      return ceil_div((long long)b.n[0] * b.n[3 - D], 64) * ceil_div(b.n[D], seg);
+      return strided_waves(b.n[0], b.n[3 - D], groups) * ceil_div(b.n[D], seg);
     }
     case K_FIELD_Y:
     case K_FIELD_Z: {
       const int D = kind - K_FIELD_X;
       const int seg = std::max(1, std::min(target, b.n[D]));
       *par = seg;
-      return ceil_div((long long)(b.n[0] + b.o[0]) * (b.n[3 - D] + b.o[3 - D]), 64) * ceil_div(b.n[D], seg);
+      return strided_waves(b.n[0] + b.o[0], b.n[3 - D] + b.o[3 - D], groups) * ceil_div(b.n[D], seg);
     }
     default: {
       const int cpl = std::max(1, target);
@@ -581,7 +587,7 @@ int Engine::build_lists() {
     d.slot = table_slots[t];
     for (int k = 0; k < K_NUM; ++k) {
       int par = 1;
-      const long long w = kind_waves(b, k, tuning.target[k], &par);
+      const long long w = kind_waves(b, k, tuning.target[k], tuning.groups[k], &par);
       if ((long long)list[k].size() + w >= (1ll << 31) / 64)
         return fail(5, "work list exceeds the launch size");
       d.wave0[k] = (int)list[k].size();
@@ -616,6 +622,7 @@ static WorkList make_wl(const Engine* e, int kind) {
   w.wave_box = static_cast<const int*>(e->lists[kind].ptr);
   w.nwaves = e->nwaves[kind];
   w.xcd_remap = e->tuning.remap[kind];
+  w.row_groups = e->tuning.groups[kind];
   return w;
 }
 
@@ -939,24 +946,25 @@ int Engine::autotune(int reps, int* chosen) {
     const bool lanes = kind == K_FLUID_X || kind == K_FIELD_X;
     const int* cand = lanes ? lanes_c : seg_c;
     const int ncand = lanes ? (int)(sizeof lanes_c / sizeof(int)) : (int)(sizeof seg_c / sizeof(int));
+    const int nord = lanes ? 1 : 2;  // pencil orders of the y/z kinds
     const int op = kind >= K_FIELD_X ? 1 : 0;
     const int d = op ? kind - K_FIELD_X : kind - K_FLUID_X;
     float best = 1e30f;
-    int best_t = tuning.target[kind];
-    int best_r = tuning.remap[kind];
-    std::vector<int> seen;
-    for (int cj = 0; cj < 2 * ncand && !rc; ++cj) {
-      const int ci = cj >> 1;
+    int best_t = tuning.target[kind], best_r = tuning.remap[kind], best_g = tuning.groups[kind];
+    std::vector<long long> seen;
+    for (int cj = 0; cj < ncand * 2 * nord && !rc; ++cj) {
+      const int ci = cj / (2 * nord), r = cj % 2, g = (cj / 2) % nord;
       tuning.target[kind] = cand[ci];
-      tuning.remap[kind] = cj & 1;
-      // skip candidates that give every box a shape already timed
-      int sig = 0;
+      tuning.remap[kind] = r;
+      tuning.groups[kind] = g;
+      // skip variants that give every box a shape already timed
+      long long sig = 0;
       for (int s : table_slots) {
         int par = 0;
-        (void)kind_waves(boxes[s], kind, cand[ci], &par);
-        sig = sig * 31 + par;
+        const long long w = kind_waves(boxes[s], kind, cand[ci], g, &par);
+        sig = sig * 1000003 + par * 7919 + w;
       }
-      sig = sig * 2 + (cj & 1);
+      sig = sig * 4 + r * 2 + g;
       if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
       seen.push_back(sig);
       if ((rc = build_lists())) break;
@@ -965,7 +973,7 @@ int Engine::autotune(int reps, int* chosen) {
       if ((rc = run_sub(op, d))) break;  // warm-up
       std::memcpy(cur, saved, sizeof cur);
       (void)hipEventRecord(e0, cfg.stream);
-      for (int r = 0; r < reps && !rc; ++r) {
+      for (int rr = 0; rr < reps && !rc; ++rr) {
         rc = run_sub(op, d);
         std::memcpy(cur, saved, sizeof cur);
       }
@@ -981,12 +989,14 @@ int Engine::autotune(int reps, int* chosen) {
       if (ms < best) {
         best = ms;
         best_t = cand[ci];
-        best_r = cj & 1;
+        best_r = r;
+        best_g = g;
       }
     }
     tuning.target[kind] = best_t;
     tuning.remap[kind] = best_r;
-    if (chosen) chosen[kind] = best_t | (best_r << 16);
+    tuning.groups[kind] = best_g;
+    if (chosen) chosen[kind] = best_t | (best_r << 16) | (best_g << 17);
     if (rc) break;
   }
   timing_mask = saved_mask;

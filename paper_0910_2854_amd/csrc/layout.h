@@ -42,6 +42,7 @@ struct WorkList {
   const int* wave_box;  // table index of the box of every wave
   int nwaves;
   int xcd_remap;        // 1: consecutive blocks of the list run on one XCD (see work_item)
+  int row_groups;       // y/z kinds: 1 = a block's waves on consecutive rows (see strided_map)
 };
 
 }  // namespace fish

@@ -399,11 +399,32 @@ __device__ __forceinline__ FluidConsts<T> fluid_consts(const FluidArgs<T>& a, in
 // every position and its boundary mapping along d) is uniform across the wave
 // and lives in scalar registers; each lane only adds its pencil offset.
 // Returns false for waves beyond the grid (the whole wave exits together).
-__device__ __forceinline__ bool strided_map(int wave, int P, int nseg, int& sg, int& p, bool& active) {
+// Two orders of the pencils (nA along x times nO along the other transverse
+// axis, p = o * nA + a): contiguous (64 consecutive pencils per wave), or,
+// with row_groups and nA >= 64, the four waves of a block on four
+// consecutive rows o over the same 64 values of a, so that the neighbouring
+// rows a sweep reads along o are mostly the block's own (L1/L2 hits).
+__device__ __forceinline__ bool strided_map(int wave, int nA, int nO, int nseg, int row_groups, int& sg, int& p,
+                                            bool& active) {
+  const int lane = (int)(threadIdx.x & 63);
+  if (row_groups && nA >= 64) {
+    const int xc = (nA + 63) >> 6;
+    const int per_seg = xc * ((nO + 3) >> 2) * 4;
+    sg = wave / per_seg;
+    if (sg >= nseg) return false;
+    const int w = wave - sg * per_seg;
+    const int g = w >> 2;
+    const int o = (g / xc) * 4 + (w & 3);
+    const int a = (g % xc) * 64 + lane;
+    active = a < nA && o < nO;
+    p = (o < nO ? o : nO - 1) * nA + (a < nA ? a : nA - 1);
+    return true;
+  }
+  const int P = nA * nO;
   const int wps = (P + 63) >> 6;
   sg = wave / wps;
   if (sg >= nseg) return false;
-  const int p0 = (wave - sg * wps) * 64 + (int)(threadIdx.x & 63);
+  const int p0 = (wave - sg * wps) * 64 + lane;
   active = p0 < P;
   p = active ? p0 : P - 1;
   return true;
@@ -424,7 +445,7 @@ __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidLaunch<T> L) {
   const int nA = g.n[A], nO = g.n[O], nD = g.n[D];
   int sg, p;
   bool active;
-  if (!strided_map(lw, nA * nO, a.nseg, sg, p, active)) return;
+  if (!strided_map(lw, nA, nO, a.nseg, L.wl.row_groups, sg, p, active)) return;
   const int s0 = sg * a.seg;
   const int s1 = min(nD, s0 + a.seg);
   int c[3];
@@ -867,7 +888,7 @@ __global__ __launch_bounds__(256) void field_strided_kernel(FieldLaunch<T> FL) {
   const int rO = g.n[O] + g.bc[O];
   int sg, p;
   bool active;
-  if (!strided_map(lw, rA * rO, a.nseg, sg, p, active)) return;
+  if (!strided_map(lw, rA, rO, a.nseg, FL.wl.row_groups, sg, p, active)) return;
   const int s0 = sg * a.seg;
   const int s1 = min(nD, s0 + a.seg);
   const bool last = (s1 == nD);
@@ -925,8 +946,12 @@ __global__ __launch_bounds__(256) void field_strided_kernel(FieldLaunch<T> FL) {
 
 // Lanes policy (d = x): waves stream whole rows (y, z) of faces, each padded
 // by 4 positions before and 4 after.
+// In FP32 the kernel needs a few registers more than three waves per SIMD
+// allow; capping it there (one spill and one reload per position) is faster
+// than running two waves (measured).
 template <typename T, int LIM>
-__global__ __launch_bounds__(256) void field_lanes_kernel(FieldLaunch<T> FL) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
+void field_lanes_kernel(FieldLaunch<T> FL) {
   constexpr int D = 0;
   const BoxDesc* d;
   int lw;
