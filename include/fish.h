@@ -161,14 +161,20 @@ enum {
  * fastest; the state is unchanged.  Shapes: stream positions per wavefront
  * for the x kinds (whole rows), segment length along the sweep for the y/z
  * kinds, each with the plain or the XCD-grouped block order (consecutive
- * blocks of a launch on one XCD, sharing its L2), and for the y/z kinds with
- * contiguous pencils per wave or the four waves of a block on four
- * consecutive rows.  targets_out (may be NULL) receives FISH_NUM_KINDS chosen
- * values: the shape in bits 0-15, the block order (1 = XCD-grouped) in bit
- * 16, the row grouping in bit 17.
+ * blocks of a launch on one XCD, sharing its L2), and with an alternative
+ * layout: for the y/z kinds the four waves of a block on four consecutive
+ * rows instead of contiguous pencils, for the x field kind two stream
+ * positions per lane instead of one.  targets_out (may be NULL) receives
+ * FISH_NUM_KINDS chosen values: the shape in bits 0-15, the block order
+ * (1 = XCD-grouped) in bit 16, the alternative layout in bit 17.
  * Results do not depend on the shapes (each cell is computed by the same
  * operations whatever wave computes it).  Synchronises the stream. */
 int fish_autotune(fish_ctx* ctx, int reps, int32_t* targets_out);
+
+/* Set one kind's work shape directly, in the encoding fish_autotune returns
+ * (for reproducing a tuned configuration).  FISH_ERR_ARG for an unknown kind
+ * or a value outside the encoding. */
+int fish_set_shape(fish_ctx* ctx, int kind, int32_t value);
 
 /* Self-test of the wavefront lane-shift primitive the x sweeps stream with
  * (no context): one wave of 64 lanes runs two iterations with lane values
@@ -261,6 +267,9 @@ int fish_batch_use_graph(fish_batch* b, int on);
 
 /* The autotuner of fish_autotune over all boxes of the batch. */
 int fish_batch_autotune(fish_batch* b, int reps, int32_t* targets_out);
+
+/* fish_set_shape for a batch. */
+int fish_batch_set_shape(fish_batch* b, int kind, int32_t value);
 
 /* Wait for the batch's stream. */
 int fish_batch_sync(fish_batch* b);

@@ -97,7 +97,7 @@ EXPORTS = ("fish_create", "fish_destroy", "fish_last_error", "fish_set_state", "
            "fish_batch_device_bytes", "fish_batch_free_bytes", "fish_batch_count", "fish_batch_add",
            "fish_batch_remove", "fish_batch_get", "fish_batch_box_info", "fish_batch_step",
            "fish_batch_use_graph", "fish_batch_autotune", "fish_batch_sync", "fish_batch_timing_enable",
-           "fish_batch_timing_read", "fish_server_create", "fish_server_destroy", "fish_server_last_error",
+           "fish_batch_timing_read", "fish_set_shape", "fish_batch_set_shape", "fish_server_create", "fish_server_destroy", "fish_server_last_error",
            "fish_server_batch", "fish_server_submit", "fish_server_pump", "fish_server_stats")
 KERNEL_FLUID, KERNEL_FIELD, KERNEL_CHECK = 1, 2, 8
 KINDS = ("fluid_x", "fluid_y", "fluid_z", "field_x", "field_y", "field_z", "check")
@@ -155,6 +155,10 @@ def load_library(path: str = LIB_PATH):
     lib.fish_batch_sync.argtypes = [vp]
     lib.fish_batch_timing_enable.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.fish_batch_timing_read.argtypes = [vp, P(ctypes.c_int), P(d)]
+    lib.fish_set_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int32]
+    lib.fish_batch_set_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int32]
+    lib.fish_set_shape.restype = ctypes.c_int
+    lib.fish_batch_set_shape.restype = ctypes.c_int
     lib.fish_server_create.argtypes = [P(BatchParams), ctypes.c_int, P(vp)]
     lib.fish_server_destroy.argtypes = [vp]
     lib.fish_server_destroy.restype = None
@@ -329,6 +333,10 @@ class Box:
         self._check(self._lib.fish_diagnostics(self._h, _dptr(out)))
         return _diag_dict(out)
 
+    def set_shape(self, kind, target, xcd_remap=0, alt_layout=0):
+        """Set one kind's work shape (kind: a name of KINDS)."""
+        self._check(self._lib.fish_set_shape(self._h, KINDS.index(kind), shape_value(target, xcd_remap, alt_layout)))
+
     def autotune(self, reps=3):
         """Pick the fastest work shape of every sweep kind; returns {kind: target}."""
         t = (ctypes.c_int32 * 7)()
@@ -337,9 +345,14 @@ class Box:
 
 
 def _tuned(t):
-    """{kind: {"target": shape, "xcd_remap": 0/1, "row_groups": 0/1}} from the autotuner's output."""
-    return {k: {"target": int(v) & 0xFFFF, "xcd_remap": (int(v) >> 16) & 1, "row_groups": (int(v) >> 17) & 1}
+    """{kind: {"target": shape, "xcd_remap": 0/1, "alt_layout": 0/1}} from the autotuner's output."""
+    return {k: {"target": int(v) & 0xFFFF, "xcd_remap": (int(v) >> 16) & 1, "alt_layout": (int(v) >> 17) & 1}
             for k, v in zip(KINDS, list(t))}
+
+
+def shape_value(target, xcd_remap=0, alt_layout=0):
+    """Encode a work shape for set_shape."""
+    return int(target) | (int(xcd_remap) << 16) | (int(alt_layout) << 17)
 
 
 def _diag_dict(out):
@@ -488,6 +501,10 @@ class Batch:
         t = (ctypes.c_int32 * 7)()
         self._check(self._lib.fish_batch_autotune(self._h, int(reps), t))
         return _tuned(t)
+
+    def set_shape(self, kind, target, xcd_remap=0, alt_layout=0):
+        self._check(self._lib.fish_batch_set_shape(self._h, KINDS.index(kind),
+                                                   shape_value(target, xcd_remap, alt_layout)))
 
     def sync(self):
         self._check(self._lib.fish_batch_sync(self._h))

@@ -57,7 +57,8 @@ struct EngineConfig {
 struct Tuning {
   int target[K_NUM];
   int remap[K_NUM];   // XCD-aware block order per kind (0/1)
-  int groups[K_NUM];  // y/z kinds: waves of a block on consecutive rows (0/1)
+  int groups[K_NUM];  // y/z kinds: waves of a block on consecutive rows; x field kind: two
+                      // stream positions per lane (0/1)
 };
 Tuning default_tuning();
 
@@ -138,6 +139,7 @@ class Engine {
   int sweep(int slot, int op, int dir, double dt);
   int diagnostics(int slot, double* out10);
   int autotune(int reps, int* chosen);
+  int set_shape(int kind, int value);
   int set_graph(bool on);
 
  private:

@@ -692,7 +692,10 @@ int Engine::field_sweep_lim() {
     const dim3 grid(grid_for((long long)L.wl.nwaves * 64));
     TimedLaunch tl(this, 2);
     if (D == 0) {
-      hipLaunchKernelGGL((field_lanes_kernel<T, LIM>), grid, dim3(kBlock), 0, cfg.stream, L);
+      if (tuning.groups[K_FIELD_X])
+        hipLaunchKernelGGL((field_lanes2_kernel<T, LIM>), grid, dim3(kBlock), 0, cfg.stream, L);
+      else
+        hipLaunchKernelGGL((field_lanes_kernel<T, LIM>), grid, dim3(kBlock), 0, cfg.stream, L);
     } else {
       constexpr int DD = D == 0 ? 1 : D;
       hipLaunchKernelGGL((field_strided_kernel<T, DD, LIM>), grid, dim3(kBlock), 0, cfg.stream, L);
@@ -823,6 +826,23 @@ int Engine::strang_step(double dt) {
   return 0;
 }
 
+// One kind's work shape in the autotuner's encoding: the shape (positions
+// per wave, segment length or cells per lane) in bits 0-15, the XCD-grouped
+// block order in bit 16, the alternative layout in bit 17.
+int Engine::set_shape(int kind, int value) {
+  if (kind < 0 || kind >= K_NUM) return fail(1, "no such kernel kind");
+  const int target = value & 0xFFFF, remap = (value >> 16) & 1, alt = (value >> 17) & 1;
+  if (target < 1 || (value >> 18) != 0) return fail(1, "bad shape value");
+  if (alt && !(kind == K_FIELD_X || kind == K_FLUID_Y || kind == K_FLUID_Z || kind == K_FIELD_Y || kind == K_FIELD_Z))
+    return fail(1, "this kind has no alternative layout");
+  tuning.target[kind] = target;
+  tuning.remap[kind] = remap;
+  tuning.groups[kind] = alt;
+  dirty = true;
+  invalidate_graph();
+  return 0;
+}
+
 int Engine::set_graph(bool on) {
   use_graph = on;
   if (!on) invalidate_graph();
@@ -946,7 +966,9 @@ int Engine::autotune(int reps, int* chosen) {
     const bool lanes = kind == K_FLUID_X || kind == K_FIELD_X;
     const int* cand = lanes ? lanes_c : seg_c;
     const int ncand = lanes ? (int)(sizeof lanes_c / sizeof(int)) : (int)(sizeof seg_c / sizeof(int));
-    const int nord = lanes ? 1 : 2;  // pencil orders of the y/z kinds
+    // second knob: the pencil order of the y/z kinds, two positions per lane
+    // for the x field sweep
+    const int nord = (lanes && kind != K_FIELD_X) ? 1 : 2;
     const int op = kind >= K_FIELD_X ? 1 : 0;
     const int d = op ? kind - K_FIELD_X : kind - K_FLUID_X;
     float best = 1e30f;

@@ -173,6 +173,11 @@ int fish_autotune(fish_ctx* c, int reps, int32_t* targets_out) {
   return rc;
 }
 
+int fish_set_shape(fish_ctx* c, int kind, int32_t value) {
+  if (!c) return FISH_ERR_ARG;
+  return c->e.set_shape(kind, value);
+}
+
 static int timing_enable(Engine& e, int mask, int max_launches) {
   if (mask < 0 || max_launches < 0 || max_launches > (1 << 20)) return e.fail(FISH_ERR_ARG, "bad timing arguments");
   int rc = e.set_device();
@@ -376,6 +381,11 @@ int fish_batch_autotune(fish_batch* b, int reps, int32_t* targets_out) {
   if (!rc && targets_out)
     for (int k = 0; k < FISH_NUM_KINDS; ++k) targets_out[k] = chosen[k];
   return rc;
+}
+
+int fish_batch_set_shape(fish_batch* b, int kind, int32_t value) {
+  if (!b) return FISH_ERR_ARG;
+  return b->e.set_shape(kind, value);
 }
 
 int fish_batch_sync(fish_batch* b) {

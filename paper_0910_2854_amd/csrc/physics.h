@@ -13,6 +13,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Multiply-adds are fused only within one source expression (never across
+// statements), so the rounding of every value is fixed by the source alone:
+// the kernels that stream the same arithmetic in different layouts (lanes,
+// pairs of positions, strided pencils, any work shape) give bitwise the same
+// result.
+#pragma clang fp contract(on)
+
 namespace fish {
 
 enum { RHO = 0, MX = 1, MY = 2, MZ = 3, EN = 4 };

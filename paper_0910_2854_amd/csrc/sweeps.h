@@ -25,6 +25,13 @@
 #include "layout.h"
 #include "physics.h"
 
+// Multiply-adds are fused only within one source expression (never across
+// statements), so the rounding of every value is fixed by the source alone:
+// the kernels that stream the same arithmetic in different layouts (lanes,
+// pairs of positions, strided pencils, any work shape) give bitwise the same
+// result.
+#pragma clang fp contract(on)
+
 namespace fish {
 
 // The wave's box and its wave index within the box; false past the list
@@ -148,14 +155,15 @@ __device__ __forceinline__ Vec<T, N> prev_vec(const Vec<T, N>& cur, const Vec<T,
 // ------------------------------------------------------------ lanes cursor
 // Position of one lane in the stream of whole rows a wave walks (lanes
 // policy): row rr of the wave's rows and position cp in [0, L) of that row.
-// Advancing by one iteration moves 64 positions; the row indices (y, z) are
-// stepped, never divided, and stay on the wave's last row past its end (those
-// lanes' positions are beyond the stream and write nothing).
+// Advancing by one iteration moves `step` positions (64, or 128 with two
+// positions per lane); the row indices (y, z) are stepped, never divided,
+// and stay on the wave's last row past its end (those lanes' positions are
+// beyond the stream and write nothing).
 struct RowCursor {
   int cp, rr, y, z;
   bool moved;
-  __device__ void init(int lane, int L, long long r0, int rows, int ny) {
-    cp = lane;
+  __device__ void init(int pos, int L, long long r0, int rows, int ny) {
+    cp = pos;
     rr = 0;
     while (cp >= L && rr < rows - 1) {
       cp -= L;
@@ -166,8 +174,8 @@ struct RowCursor {
     z = (int)(row / ny);
     moved = true;
   }
-  __device__ void advance(int L, int rows, int ny) {
-    cp += 64;
+  __device__ void advance(int L, int rows, int ny, int step = 64) {
+    cp += step;
     moved = false;
     while (cp >= L && rr < rows - 1) {
       cp -= L;
@@ -181,20 +189,21 @@ struct RowCursor {
   }
 };
 
-// Cheap wrap for indices within one period of the box (the slow path only
-// for boxes thinner than the stencil halo).
+// Branch-free maps for indices the stencils reach from a box row, i in
+// [-8, n + 4): a clamp on outflow axes, at most one period added or removed
+// on periodic ones (boxes thinner than 8 cells take the general wrap).  bc and
+// n are uniform across the wave, so the choice of path is a scalar branch.
 __device__ __forceinline__ int map_cell_near(int i, int n, int bc) {
-  if (i >= 0 && i < n) return i;
-  if (bc == 0) {
-    if (i < 0 && i + n >= 0) return i + n;
-    if (i >= n && i - n < n) return i - n;
-    return wrap(i, n);
+  if (bc) return min(max(i, 0), n - 1);
+  if (n >= 8) {
+    i += i < 0 ? n : 0;
+    return i >= n ? i - n : i;
   }
-  return i < 0 ? 0 : n - 1;
+  return wrap(i, n);
 }
 __device__ __forceinline__ int map_face_near(int i, int n, int bc) {
-  if (bc == 0) return map_cell_near(i, n, 0);
-  return i < 0 ? 0 : (i > n ? n : i);
+  if (bc) return min(max(i, 0), n);
+  return map_cell_near(i, n, 0);
 }
 
 // ------------------------------------------------------------ L_d pipeline
@@ -603,7 +612,10 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
     }
     In in;
     in.valid = (it << 6) + lane < npos;
-    const int cpos = rc.cp - 3;  // cell index along x (-3 .. nx+2)
+    // cell index along x (-3 .. nx+2); lanes past the end of the stream sit
+    // on the wave's last row with cp >= L and are clamped into it, so that
+    // every index they map stays in the box (they store nothing)
+    const int cpos = min(rc.cp, L - 1) - 3;
     in.co = cpos - 3;
     const unsigned ms = (base + (unsigned)map_cell_near(cpos, nx, g.bc[0])) * z4;
 #pragma unroll
@@ -800,6 +812,27 @@ __device__ __forceinline__ FieldOffsets field_offsets(const Geo& g, int c1, int 
   return o;
 }
 
+// The same offsets for the x sweep's rows (t1 = y, t2 = z) in 32-bit element
+// arithmetic, with the cheap maps (the neighbours are within one period).
+struct RowOffsets {
+  unsigned base, ownc;             // face row (c1, c2) and its mapped own cell
+  int c1m, c1p, c2m, c2p, f1p, f2p;
+};
+
+__device__ __forceinline__ void row_offsets(const Geo& g, int c1, int c2, RowOffsets& r) {
+  const int st1 = (int)g.st[1], st2 = (int)g.st[2];
+  const int n1 = g.n[1], n2 = g.n[2], b1 = g.bc[1], b2 = g.bc[2];
+  const int m1 = map_cell_near(c1, n1, b1), m2 = map_cell_near(c2, n2, b2);
+  r.base = (unsigned)(c1 * st1 + c2 * st2);
+  r.ownc = (unsigned)(m1 * st1 + m2 * st2);
+  r.c1m = (map_cell_near(c1 - 1, n1, b1) - m1) * st1;
+  r.c1p = (map_cell_near(c1 + 1, n1, b1) - m1) * st1;
+  r.c2m = (map_cell_near(c2 - 1, n2, b2) - m2) * st2;
+  r.c2p = (map_cell_near(c2 + 1, n2, b2) - m2) * st2;
+  r.f1p = (map_face_near(c1 + 1, n1, b1) - c1) * st1;
+  r.f2p = (map_face_near(c2 + 1, n2, b2) - c2) * st2;
+}
+
 // Byte offsets of everything one position reads, relative to the arrays'
 // base pointers (which carry the d offset when it is wave-uniform).
 struct FieldLane {
@@ -980,8 +1013,7 @@ void field_lanes_kernel(FieldLaunch<T> FL) {
   }
   RowCursor rc;
   rc.init(lane, L, r0, rows, ry);
-  long long base = 0, ownc = 0;
-  FieldOffsets o;
+  RowOffsets ro;
   bool own1 = false, own2 = false;
   struct In {
     FieldIn<T> f;
@@ -989,29 +1021,36 @@ void field_lanes_kernel(FieldLaunch<T> FL) {
     int cpos;
     bool valid, own1, own2;
   };
+  constexpr unsigned z = sizeof(T);
   auto load = [&](int it) {
     if (rc.moved) {
-      const int c1 = rc.y, c2 = rc.z;  // y, z face rows
-      base = (long long)c1 * g.st[1] + (long long)c2 * g.st[2];
-      ownc = (long long)map_cell_near(c1, g.n[1], g.bc[1]) * g.st[1] +
-             (long long)map_cell_near(c2, g.n[2], g.bc[2]) * g.st[2];
-      o = field_offsets<D>(g, c1, c2);
-      own1 = c2 < g.n[2];
-      own2 = c1 < g.n[1];
+      row_offsets(g, rc.y, rc.z, ro);  // y, z face rows
+      own1 = rc.z < g.n[2];
+      own2 = rc.y < g.n[1];
     }
     In in;
     in.valid = (it << 6) + lane < npos;
-    in.cpos = rc.cp - 4;  // cell index along x (-4 .. nx+3)
+    in.cpos = min(rc.cp, L - 1) - 4;  // cell index along x (-4 .. nx+3), clamped as in the fluid sweep
     in.own1 = own1;
     in.own2 = own2;
-    const int mx = map_cell_near(in.cpos, nx, g.bc[0]);
-    const int m4 = map_cell_near(in.cpos - 4, nx, g.bc[0]);
-    const FieldLane l = field_lane<T>(base, ownc, o, mx);
+    const unsigned mx = (unsigned)map_cell_near(in.cpos, nx, g.bc[0]);
+    const unsigned m4 = (unsigned)map_cell_near(in.cpos - 4, nx, g.bc[0]);
+    FieldLane l;
+    const unsigned oc = ro.ownc + mx;
+    l.cc = oc * z;
+    l.c1m = (oc + ro.c1m) * z;
+    l.c1p = (oc + ro.c1p) * z;
+    l.c2m = (oc + ro.c2m) * z;
+    l.c2p = (oc + ro.c2p) * z;
+    l.fA = (ro.base + mx) * z;
+    l.fB = (ro.base + mx + ro.f1p) * z;
+    l.fC = l.fA;
+    l.fD = (ro.base + mx + ro.f2p) * z;
     in.f = field_load<T>(a.md, a.rho, a.bt[0], a.bt[1], l);
-    in.b4off = (unsigned)((base + m4) * (long long)sizeof(T));
+    in.b4off = (ro.base + m4) * z;
     in.f.b4a = ld(a.bt[0], in.b4off);
     in.f.b4c = ld(a.bt[1], in.b4off);
-    in.fo = (unsigned)((base + max(in.cpos - 3, 0)) * (long long)sizeof(T));
+    in.fo = (ro.base + (unsigned)max(in.cpos - 3, 0)) * z;
     rc.advance(L, rows, ry);
     return in;
   };
@@ -1033,6 +1072,177 @@ void field_lanes_kernel(FieldLaunch<T> FL) {
     compute(cur, hA, hB);
     cur = load(it + 2);
     compute(nxt, hB, hA);
+  }
+}
+
+// ------------------------------------------------------------ B_x, two positions per lane
+// The x field sweep with lane l holding stream positions 2l and 2l+1 of a
+// 128-position window.  The pipeline runs stage by stage over both: the
+// value one position back is the lane's own register for 2l+1 and the
+// neighbour lane's (one DPP shift, lane 0 taking lane 63 of the previous
+// window) for 2l, so each history value costs one shift per two cells.
+template <typename T>
+__device__ __forceinline__ void prev2(const T (&x)[2], T (&p)[2], T& carry) {
+  p[1] = x[0];
+  p[0] = lane_prev(x[1], carry);
+}
+
+// row_position for both positions of the lane; h holds the carries.
+template <typename T, int LIM, bool NEED_BN>
+__device__ __forceinline__ void row_position2(const T (&w0)[2], const T (&bb)[2], const T (&b4)[2], T k_half,
+                                              T k_full, RowHist<T>& h, T (&bn)[2], T (&P2c)[2]) {
+  T w1[2], w2[2], vbc[2], b1[2], fc[2], vb1[2], V[2], f2[2], P1[2], p1[2], b2[2], bp[2], fp2[2];
+  T vb2[2], vb3[2], fp3[2], fp4[2], fp5[2];
+  prev2(w0, w1, h.w1);
+  prev2(w1, w2, h.w2);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) vbc[j] = T(0.25) * (w2[j] + T(2) * w1[j] + w0[j]);  // v-bar of c-1
+  prev2(bb, b1, h.b1);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) fc[j] = vbc[j] * b1[j];
+  prev2(vbc, vb1, h.vb1);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) V[j] = T(0.5) * (vb1[j] + vbc[j]);
+  prev2(fc, f2, h.f2);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) P1[j] = V[j] > T(0) ? f2[j] : fc[j];
+  prev2(P1, p1, h.p1);
+  prev2(b1, b2, h.b2);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    bp[j] = b2[j] - k_half * (P1[j] - p1[j]);
+    fp2[j] = vb1[j] * bp[j];
+  }
+  prev2(vb1, vb2, h.vb2);
+  prev2(vb2, vb3, h.vb3);
+  prev2(fp2, fp3, h.fp3);
+  prev2(fp3, fp4, h.fp4);
+  prev2(fp4, fp5, h.fp5);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const T V7 = T(0.5) * (vb3[j] + vb2[j]);
+    const T up = fp4[j] + T(0.5) * limit<T, LIM>(fp4[j] - fp5[j], fp3[j] - fp4[j]);
+    const T dn = fp3[j] - T(0.5) * limit<T, LIM>(fp3[j] - fp4[j], fp2[j] - fp3[j]);
+    P2c[j] = V7 > T(0) ? up : dn;
+  }
+  if (NEED_BN) {
+    T P2[2];
+    prev2(P2c, P2, h.P2);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bn[j] = b4[j] - k_full * (P2c[j] - P2[j]);
+  }
+}
+
+template <typename T, int LIM>
+__global__ __launch_bounds__(256) void field_lanes2_kernel(FieldLaunch<T> FL) {
+  constexpr int D = 0;
+  const BoxDesc* d;
+  int lw;
+  if (!work_item<K_FIELD_X>(FL.wl, d, lw)) return;
+  const FieldArgs<T> a = field_view<T, K_FIELD_X>(FL, *d);
+  const Geo& g = a.g;
+  const int nx = g.n[0];
+  const bool outx = g.bc[0] == 1;
+  const int L = nx + 8;
+  const int ry = g.n[1] + g.bc[1];
+  const int rz = g.n[2] + g.bc[2];
+  const long long nrows = (long long)ry * rz;
+  const int lane = threadIdx.x & 63;
+  const long long r0 = (long long)lw * a.rows_per_wave;
+  if (r0 >= nrows) return;  // whole wave exits together
+  const int rows = (int)min((long long)a.rows_per_wave, nrows - r0);
+  const int npos = rows * L;
+  const int nit = (npos + 127) >> 7;
+  const FieldConsts<T> k = field_consts<T, D>(a);
+  RowHist<T> h[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) h[q].zero();
+  RowCursor rc[2];
+  RowOffsets ro[2];
+  bool own1[2] = {false, false}, own2[2] = {false, false};
+#pragma unroll
+  for (int j = 0; j < 2; ++j) rc[j].init(2 * lane + j, L, r0, rows, ry);
+  constexpr unsigned z = sizeof(T);
+  struct In {
+    FieldIn<T> f;
+    unsigned b4off, fo;
+    int cpos;
+    bool valid, own1, own2;
+  };
+  auto load1 = [&](int it, int j) {
+    if (rc[j].moved) {
+      row_offsets(g, rc[j].y, rc[j].z, ro[j]);
+      own1[j] = rc[j].z < g.n[2];
+      own2[j] = rc[j].y < g.n[1];
+    }
+    In in;
+    in.valid = (it << 7) + 2 * lane + j < npos;
+    in.cpos = min(rc[j].cp, L - 1) - 4;  // clamped as in the fluid sweep
+    in.own1 = own1[j];
+    in.own2 = own2[j];
+    const unsigned mx = (unsigned)map_cell_near(in.cpos, nx, g.bc[0]);
+    const unsigned m4 = (unsigned)map_cell_near(in.cpos - 4, nx, g.bc[0]);
+    FieldLane l;
+    const unsigned oc = ro[j].ownc + mx;
+    l.cc = oc * z;
+    l.c1m = (oc + ro[j].c1m) * z;
+    l.c1p = (oc + ro[j].c1p) * z;
+    l.c2m = (oc + ro[j].c2m) * z;
+    l.c2p = (oc + ro[j].c2p) * z;
+    l.fA = (ro[j].base + mx) * z;
+    l.fB = (ro[j].base + mx + ro[j].f1p) * z;
+    l.fC = l.fA;
+    l.fD = (ro[j].base + mx + ro[j].f2p) * z;
+    in.f = field_load<T>(a.md, a.rho, a.bt[0], a.bt[1], l);
+    in.b4off = (ro[j].base + m4) * z;
+    in.f.b4a = ld(a.bt[0], in.b4off);
+    in.f.b4c = ld(a.bt[1], in.b4off);
+    in.fo = (ro[j].base + (unsigned)max(in.cpos - 3, 0)) * z;
+    rc[j].advance(L, rows, ry, 128);
+    return in;
+  };
+  auto compute = [&](const In (&in)[2]) {
+    T wA[2], wB[2], wC[2], wD[2], bA[2], bB[2], bC[2], bD[2], b4a[2], b4c[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      T v[5];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) v[i] = in[j].f.md[i] * rcp(in[j].f.rho[i]);
+      wA[j] = T(0.5) * (v[1] + v[0]);
+      wB[j] = T(0.5) * (v[0] + v[2]);
+      wC[j] = T(0.5) * (v[3] + v[0]);
+      wD[j] = T(0.5) * (v[0] + v[4]);
+      bA[j] = in[j].f.b[0];
+      bB[j] = in[j].f.b[1];
+      bC[j] = in[j].f.b[2];
+      bD[j] = in[j].f.b[3];
+      b4a[j] = in[j].f.b4a;
+      b4c[j] = in[j].f.b4c;
+    }
+    T bn1[2], bn2[2], eA[2], eB[2], eC[2], eD[2], dummy[2];
+    row_position2<T, LIM, true>(wA, bA, b4a, k.k_half, k.k_full, h[0], bn1, eA);
+    row_position2<T, LIM, false>(wB, bB, b4a, k.k_half, k.k_full, h[1], dummy, eB);
+    row_position2<T, LIM, true>(wC, bC, b4c, k.k_half, k.k_full, h[2], bn2, eC);
+    row_position2<T, LIM, false>(wD, bD, b4c, k.k_half, k.k_full, h[3], dummy, eD);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      // Eq. (64), physical signs
+      const T dbd = k.dt * ((eB[j] - eA[j]) * k.ih1 + (eD[j] - eC[j]) * k.ih2);
+      const int cb = in[j].cpos - 4;
+      if (in[j].valid && cb >= 0 && cb < nx) {
+        if (in[j].own1) st(a.bto[0], in[j].b4off, bn1[j]);
+        if (in[j].own2) st(a.bto[1], in[j].b4off, bn2[j]);
+      }
+      const int fd = in[j].cpos - 3;
+      if (in[j].valid && in[j].own1 && in[j].own2 && fd >= 0 && (fd < nx || (outx && fd == nx)))
+        st(a.bdo, in[j].fo, ld(a.bd, in[j].fo) + dbd);
+    }
+  };
+  for (int it = 0; it < nit; ++it) {
+    In in[2];
+    in[0] = load1(it, 0);
+    in[1] = load1(it, 1);
+    compute(in);
   }
 }
 
