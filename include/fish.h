@@ -164,7 +164,9 @@ enum {
  * blocks of a launch on one XCD, sharing its L2), and with an alternative
  * layout: for the y/z kinds the four waves of a block on four consecutive
  * rows instead of contiguous pencils, for the x field kind two stream
- * positions per lane instead of one.  targets_out (may be NULL) receives
+ * positions per lane instead of one, for the check kind the CFL speed of a
+ * step's new state reduced by the check kernel after the last x sweep
+ * instead of inside it (the same value either way).  targets_out (may be NULL) receives
  * FISH_NUM_KINDS chosen values: the shape in bits 0-15, the block order
  * (1 = XCD-grouped) in bit 16, the alternative layout in bit 17.
  * Results do not depend on the shapes (each cell is computed by the same

@@ -210,7 +210,10 @@ class _TorchAllocator:
                 return None
 
         def free(ptr, nbytes, stream, user):
-            torch.cuda.caching_allocator_delete(ptr)
+            try:
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:  # interpreter shutdown: torch is gone, the process frees the memory
+                pass
 
         self.alloc = _ALLOC(alloc)
         self.free = _FREE(free)

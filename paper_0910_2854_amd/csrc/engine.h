@@ -58,7 +58,8 @@ struct Tuning {
   int target[K_NUM];
   int remap[K_NUM];   // XCD-aware block order per kind (0/1)
   int groups[K_NUM];  // y/z kinds: waves of a block on consecutive rows; x field kind: two
-                      // stream positions per lane (0/1)
+                      // stream positions per lane; check kind: the step's CFL reduction in
+                      // the check kernel instead of the last x sweep (0/1)
 };
 Tuning default_tuning();
 
@@ -149,6 +150,7 @@ class Engine {
   int launch_check();
   int run_sub(int op, int d);
   int enqueue_step_cfl();                   // the launches of one CFL-stepped double step
+  int last_sweep_and_cfl();
   void invalidate_graph();
   void drop_retired_graphs();
   int build_lists();

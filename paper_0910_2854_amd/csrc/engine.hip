@@ -777,13 +777,28 @@ int Engine::enqueue_step_cfl() {
     if ((rc = run_sub(0, d))) return rc;
   }
   if ((rc = run_sub(1, 0))) return rc;
+  if ((rc = last_sweep_and_cfl())) return rc;
+  hipLaunchKernelGGL(advance_time_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream, tb, nb, sc);
+  return launch_check();
+}
+
+// The last L_x of a step and the CFL speed of the state it leaves: reduced by
+// the sweep itself, or by the check kernel after it (tuning choice; the same
+// per-cell function, so the same value either way).
+int Engine::last_sweep_and_cfl() {
+  const int nb = (int)table_slots.size();
+  const BoxDesc* tb = (const BoxDesc*)table.ptr;
+  Scalars* sc = (Scalars*)scal.ptr;
+  int rc;
+  if (tuning.groups[K_CHECK]) {
+    if ((rc = run_sub(0, 0))) return rc;
+    return esize == 8 ? launch_check_cfl<double>() : launch_check_cfl<float>();  // resets cmax first
+  }
   hipLaunchKernelGGL(reset_cmax_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream, tb, nb, sc);
   last_fluid_cfl = true;
   rc = run_sub(0, 0);
   last_fluid_cfl = false;
-  if (rc) return rc;
-  hipLaunchKernelGGL(advance_time_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream, tb, nb, sc);
-  return launch_check();
+  return rc;
 }
 
 int Engine::strang_step(double dt) {
@@ -811,13 +826,8 @@ int Engine::strang_step(double dt) {
       if ((rc = run_sub(0, d))) return rc;
     }
     if ((rc = run_sub(1, 0))) return rc;
+    if ((rc = last_sweep_and_cfl())) return rc;
     const int nb = (int)table_slots.size();
-    hipLaunchKernelGGL(reset_cmax_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream,
-                       (const BoxDesc*)table.ptr, nb, (Scalars*)scal.ptr);
-    last_fluid_cfl = true;
-    rc = run_sub(0, 0);
-    last_fluid_cfl = false;
-    if (rc) return rc;
     hipLaunchKernelGGL(advance_time_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream,
                        (const BoxDesc*)table.ptr, nb, (Scalars*)scal.ptr);
     if ((rc = launch_check())) return rc;
@@ -833,7 +843,7 @@ int Engine::set_shape(int kind, int value) {
   if (kind < 0 || kind >= K_NUM) return fail(1, "no such kernel kind");
   const int target = value & 0xFFFF, remap = (value >> 16) & 1, alt = (value >> 17) & 1;
   if (target < 1 || (value >> 18) != 0) return fail(1, "bad shape value");
-  if (alt && !(kind == K_FIELD_X || kind == K_FLUID_Y || kind == K_FLUID_Z || kind == K_FIELD_Y || kind == K_FIELD_Z))
+  if (alt && kind == K_FLUID_X)
     return fail(1, "this kind has no alternative layout");
   tuning.target[kind] = target;
   tuning.remap[kind] = remap;
@@ -1021,12 +1031,47 @@ int Engine::autotune(int reps, int* chosen) {
     if (chosen) chosen[kind] = best_t | (best_r << 16) | (best_g << 17);
     if (rc) break;
   }
+  // the CFL speed of a step's new state: fused into the last x sweep, or the
+  // check kernel after a plain one (both time the x sweep too)
+  if (!rc) {
+    if ((rc = build_lists())) goto done;
+    float tbest = 1e30f;
+    int gbest = tuning.groups[K_CHECK];
+    for (int gsel = 0; gsel < 2 && !rc; ++gsel) {
+      tuning.groups[K_CHECK] = gsel;
+      int saved[8];
+      std::memcpy(saved, cur, sizeof cur);
+      if ((rc = last_sweep_and_cfl())) break;  // warm-up
+      std::memcpy(cur, saved, sizeof cur);
+      (void)hipEventRecord(e0, cfg.stream);
+      for (int rr = 0; rr < reps && !rc; ++rr) {
+        rc = last_sweep_and_cfl();
+        std::memcpy(cur, saved, sizeof cur);
+      }
+      (void)hipEventRecord(e1, cfg.stream);
+      if (rc) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = fail(3, "hipEventSynchronize failed");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < tbest) {
+        tbest = ms;
+        gbest = gsel;
+      }
+    }
+    tuning.groups[K_CHECK] = gbest;
+  }
+done:
   timing_mask = saved_mask;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (chosen) chosen[K_CHECK] = tuning.target[K_CHECK];
+  if (chosen) chosen[K_CHECK] = tuning.target[K_CHECK] | (tuning.groups[K_CHECK] << 17);
   dirty = true;
   int rc2 = ensure_table();
+  // the timed sweeps left the CFL speeds of other states: reduce the current one again
+  if (!rc && !rc2) rc2 = check_cfl_all();
   return rc ? rc : rc2;
 }
 

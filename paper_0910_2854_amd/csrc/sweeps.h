@@ -518,32 +518,42 @@ __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidLaunch<T> L) {
   }
 }
 
-// CFL speed of one cell for Eq. (14)-(15): max over active axes of
-// (|v_d| + c_F,d)/h_d, with the pressure recovered in FP64; also flags a bad
-// state (rho <= 0, p <= 0 or a non-finite value).
+// Speeds of one cell for Eq. (14)-(15): sp[d] = |v_d| + c_F,d on the active
+// axes (0 on an axis with one cell), with the pressure recovered in FP64;
+// also flags a bad state (rho <= 0, p <= 0 or a non-finite value).  The
+// division by h_d is left to cfl_of: it is monotonic, so the maximum of the
+// divided speeds is the divided maximum, bitwise.
 template <typename T>
-__device__ __forceinline__ double cell_cfl_speed(const T* u, const T* b, double gamma, const Geo& g, int& bad) {
+__device__ __forceinline__ void cell_cfl_speeds(const T* u, const T* b, double gamma, const Geo& g, double* sp,
+                                                int& bad) {
   T b2;
   const T p = pressure<T>(u, b, gamma - 1.0, &b2);
   const T ri = rcp(u[RHO]);
   const T a2 = (T)gamma * p * ri;
   const T q = a2 + b2 * ri;
-  double cmax = 0.0;
   bool ok = u[RHO] > T(0) && p > T(0);
 #pragma unroll
   for (int i = 0; i < 5; ++i) ok = ok && isfinite(u[i]);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
+    sp[d] = 0.0;
     if (g.n[d] > 1) {
       const T disc = q * q - T(4) * a2 * b[d] * b[d] * ri;
       const T cf = fsqrt(T(0.5) * (q + fsqrt(disc < T(0) ? T(0) : disc)));
-      const double sp = ((double)fabs(u[MX + d] * ri) + (double)cf) / g.h[d];
-      ok = ok && isfinite(sp);
-      cmax = fmax(cmax, sp);
+      sp[d] = (double)fabs(u[MX + d] * ri) + (double)cf;
+      ok = ok && isfinite(sp[d]);
     }
   }
   if (!ok) bad = 1;
-  return cmax;
+}
+
+// max over the active axes of smax[d] / h_d (Eq. 15).
+__device__ __forceinline__ double cfl_of(const double* smax, const Geo& g) {
+  double c = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (g.n[d] > 1) c = fmax(c, smax[d] / g.h[d]);
+  return c;
 }
 
 // Reduce (cmax, bad) over the wave and publish with one atomic per wave.
@@ -587,7 +597,7 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
   FluidHist<T, HSE> hA, hB;
   hA.zero();
   hB.zero();
-  double cmax = 0.0;
+  double smax[3] = {0.0, 0.0, 0.0};
   int bad = 0;
   RowCursor rc;
   rc.init(lane, L, r0, rows, ny);
@@ -649,9 +659,11 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
     }
     if (CFL) {
       int cell_bad = 0;
-      const double sp = cell_cfl_speed<T>(un, in.b3, a.gamma, g, cell_bad);
+      double sp[3];
+      cell_cfl_speeds<T>(un, in.b3, a.gamma, g, sp, cell_bad);
       if (out) {
-        cmax = fmax(cmax, sp);
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) smax[dd] = fmax(smax[dd], sp[dd]);
         bad |= cell_bad;
       }
     }
@@ -663,7 +675,7 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
     cur = load(it + 2);
     compute(nxt, hB, hA);
   }
-  if (CFL) publish_cfl(cmax, bad, const_cast<Scalars*>(a.sc));
+  if (CFL) publish_cfl(cfl_of(smax, g), bad, const_cast<Scalars*>(a.sc));
 }
 
 // ------------------------------------------------------------ B_d (fused)
@@ -1259,7 +1271,8 @@ struct CheckLaunch {
 // Eq. (14)-(15) on the stored state: the CFL speed of every cell (the same
 // function, hence bitwise the same value, as the reduction fused into the
 // last sweep of a step) and the state check (rho > 0, p > 0, every value
-// finite).  A wave covers 64 * par consecutive cells of its box.
+// finite).  A wave covers 64 * par consecutive cells of its box (x fastest);
+// each lane steps its cell index by 64, never dividing inside the loop.
 template <typename T>
 __global__ __launch_bounds__(256) void check_cfl_kernel(CheckLaunch<T> L) {
   const BoxDesc* d;
@@ -1267,30 +1280,52 @@ __global__ __launch_bounds__(256) void check_cfl_kernel(CheckLaunch<T> L) {
   if (!work_item<K_CHECK>(L.wl, d, lw)) return;
   const Geo g = d->g;
   const long long off = d->off;
-  const long long ncell = (long long)g.n[0] * g.n[1] * g.n[2];
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+  const long long ncell = (long long)n0 * n1 * n2;
   const long long c0 = (long long)lw * 64 * d->par[K_CHECK];
   const long long c1 = min(ncell, c0 + 64ll * d->par[K_CHECK]);
-  double cmax = 0.0;
-  int bad = 0;
-  for (long long cidx = c0 + (threadIdx.x & 63); cidx < c1; cidx += 64) {
-    const int i = (int)(cidx % g.n[0]);
-    const long long r = cidx / g.n[0];
-    const int j = (int)(r % g.n[1]);
-    const int k = (int)(r / g.n[1]);
-    const long long s = off + (long long)i * g.st[0] + (long long)j * g.st[1] + (long long)k * g.st[2];
-    T u[5], b[3];
+  const T* u[5];
+  const T* b[3];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) u[f] = L.u[f][s];
-    const long long sx = s + (long long)(map_face(i + 1, g.n[0], g.bc[0]) - i) * g.st[0];
-    const long long sy = s + (long long)(map_face(j + 1, g.n[1], g.bc[1]) - j) * g.st[1];
-    const long long sz = s + (long long)(map_face(k + 1, g.n[2], g.bc[2]) - k) * g.st[2];
-    b[0] = T(0.5) * (L.b[0][s] + L.b[0][sx]);
-    b[1] = T(0.5) * (L.b[1][s] + L.b[1][sy]);
-    b[2] = T(0.5) * (L.b[2][s] + L.b[2][sz]);
-    if (!isfinite(b[0]) || !isfinite(b[1]) || !isfinite(b[2])) bad = 1;
-    cmax = fmax(cmax, cell_cfl_speed<T>(u, b, L.gamma, g, bad));
+  for (int f = 0; f < 5; ++f) u[f] = L.u[f] + off;
+#pragma unroll
+  for (int f = 0; f < 3; ++f) b[f] = L.b[f] + off;
+  const unsigned st1 = (unsigned)g.st[1], st2 = (unsigned)g.st[2];
+  constexpr unsigned z4 = sizeof(T);
+  long long c = c0 + (threadIdx.x & 63);
+  int x = (int)(c % n0);
+  const long long r = c / n0;
+  int y = (int)(r % n1);
+  int zz = (int)(r / n1);
+  double smax[3] = {0.0, 0.0, 0.0};
+  int bad = 0;
+  for (; c < c1; c += 64) {
+    const unsigned s = (unsigned)x + (unsigned)y * st1 + (unsigned)zz * st2;
+    const unsigned o = s * z4;
+    T uc[5], bc[3];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) uc[f] = ld(u[f], o);
+    const unsigned sx = (unsigned)(map_face_near(x + 1, n0, g.bc[0]) - x);
+    const unsigned sy = (unsigned)(map_face_near(y + 1, n1, g.bc[1]) - y) * st1;
+    const unsigned sz = (unsigned)(map_face_near(zz + 1, n2, g.bc[2]) - zz) * st2;
+    bc[0] = T(0.5) * (ld(b[0], o) + ld(b[0], (s + sx) * z4));
+    bc[1] = T(0.5) * (ld(b[1], o) + ld(b[1], (s + sy) * z4));
+    bc[2] = T(0.5) * (ld(b[2], o) + ld(b[2], (s + sz) * z4));
+    if (!isfinite(bc[0]) || !isfinite(bc[1]) || !isfinite(bc[2])) bad = 1;
+    double sp[3];
+    cell_cfl_speeds<T>(uc, bc, L.gamma, g, sp, bad);
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) smax[dd] = fmax(smax[dd], sp[dd]);
+    x += 64;
+    while (x >= n0) {
+      x -= n0;
+      if (++y == n1) {
+        y = 0;
+        ++zz;
+      }
+    }
   }
-  publish_cfl(cmax, bad, L.sc + d->slot);
+  publish_cfl(cfl_of(smax, g), bad, L.sc + d->slot);
 }
 
 // Per-box step scalars; one thread per box of the table.

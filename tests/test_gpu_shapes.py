@@ -33,6 +33,7 @@ def _run(n, bc, st, prec, variant):
         g.set_shape("field_x", xt, remap, alt)
         for kind in ("fluid_y", "fluid_z", "field_y", "field_z"):
             g.set_shape(kind, seg, remap, alt)
+        g.set_shape("check", 16 if alt else 4, remap, alt)  # alt: CFL in the check kernel, not the last sweep
     for _ in range(2):
         g.strang_step(0.0)
     out = g.get_state()
@@ -63,5 +64,5 @@ def test_set_shape_rejects_bad_values():
     with pytest.raises(fish.FishError):
         g.set_shape("fluid_x", 0)
     with pytest.raises(fish.FishError):
-        g.set_shape("check", 16, 0, 1)  # no alternative layout for the CFL check
+        g.set_shape("fluid_x", 768, 0, 1)  # no alternative layout for the x fluid sweep
     g.close()
