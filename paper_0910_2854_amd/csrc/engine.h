@@ -35,6 +35,8 @@ struct HostBox {
   long long nelem = 0;      // elements per array
   long long off = 0;        // element offset in every pool
   long long reserved = 0;   // elements reserved in the pools (aligned)
+  bool parked = false;      // kept (state readable) but out of the launches
+  hipEvent_t ready = nullptr;  // parked: completes after the last launch that touched the box
 };
 
 struct EngineConfig {
@@ -83,11 +85,25 @@ class Engine {
   DeviceBuf partial, diag_out;
   int npartial = 1024;
 
-  // device table and work lists (rebuilt when the set of boxes changes)
+  // device table and work lists (rebuilt when the set of boxes changes); two
+  // sets alternate, so that a rebuild never waits for launches still reading
+  // the current one
   DeviceBuf table;
   DeviceBuf lists[K_NUM];
   int nwaves[K_NUM]{};
   std::vector<int> table_slots;
+  void* list_host = nullptr;       // pinned staging of the uploads into this set
+  size_t list_host_bytes = 0;
+  hipEvent_t list_done = nullptr;  // recorded when this set stops being current
+  struct ListSet {
+    DeviceBuf table;
+    DeviceBuf lists[K_NUM];
+    int nwaves[K_NUM]{};
+    std::vector<int> slots;
+    void* host = nullptr;
+    size_t host_bytes = 0;
+    hipEvent_t done = nullptr;
+  } spare;
   bool dirty = true;
   Tuning tuning = default_tuning();
 
@@ -96,7 +112,12 @@ class Engine {
   bool graph_ok = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  std::vector<std::pair<hipGraph_t, hipGraphExec_t>> retired_graphs;
+  struct RetiredGraph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    hipEvent_t after;  // completes after every launch of the graph
+  };
+  std::vector<RetiredGraph> retired_graphs;
 
   bool last_fluid_cfl = false;
 
@@ -125,16 +146,19 @@ class Engine {
   long long box_elems(const int n[3], const int bc[3]) const;
   int add_box(const int n[3], const double h[3], const int bc[3], double cfl, int* slot);
   int remove_box(int slot);
+  int park(int slot);
   int upload(int slot, const double* cell5, const double* bx, const double* by, const double* bz,
              const double* phi_in);
   int download(int slot, double* cell5, double* bx, double* by, double* bz);
   int read_scalars(int slot, Scalars* out);
+  int read_scalars_parked(int slot, Scalars* out);
   int count() const;
   long long free_elems() const;
 
   // stepping
   int ensure_table();
   int check_cfl_all();
+  int check_new();
   int strang_step(double dt);               // every box of the table
   int steps(int nsteps);                    // CFL-stepped double steps, graph when enabled
   int sweep(int slot, int op, int dir, double dt);

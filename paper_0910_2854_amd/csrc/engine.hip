@@ -119,10 +119,13 @@ int Engine::init(const EngineConfig& c, long long cap_elems, int max_boxes) {
   if (!rc && cfg.gravity) rc = dev_alloc(phi, bytes);
   if (!rc) rc = dev_alloc(scal, sizeof(Scalars) * (size_t)max_boxes);
   if (!rc) rc = dev_alloc(table, sizeof(BoxDesc) * (size_t)max_boxes);
+  if (!rc) rc = dev_alloc(spare.table, sizeof(BoxDesc) * (size_t)max_boxes);
   if (!rc) rc = dev_alloc(partial, (size_t)npartial * 10 * sizeof(double));
   if (!rc) rc = dev_alloc(diag_out, 16 * sizeof(double));
   if (rc) return rc;
   HIP_TRY(hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&list_done, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&spare.done, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&copy_ev, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&compute_ev, hipEventDisableTiming));
   for (int b = 0; b < 2; ++b) HIP_TRY(hipEventCreateWithFlags(&stage_ev[b], hipEventDisableTiming));
@@ -167,25 +170,53 @@ void Engine::release() {
   dev_free(scal);
   dev_free(table);
   for (int k = 0; k < K_NUM; ++k) dev_free(lists[k]);
+  dev_free(spare.table);
+  for (int k = 0; k < K_NUM; ++k) dev_free(spare.lists[k]);
+  for (void* h : {list_host, spare.host})
+    if (h) (void)hipHostFree(h);
+  list_host = spare.host = nullptr;
+  for (hipEvent_t ev : {list_done, spare.done})
+    if (ev) (void)hipEventDestroy(ev);
+  list_done = spare.done = nullptr;
+  for (auto& b : boxes)
+    if (b.ready) {
+      (void)hipEventDestroy(b.ready);
+      b.ready = nullptr;
+    }
   dev_free(partial);
   dev_free(diag_out);
 }
 
-// A graph may still be executing when the set of boxes changes: it is only
-// destroyed after the next synchronisation of the stream.
+// A graph may still be executing when the set of boxes changes: it is
+// destroyed once an event recorded behind its launches has completed.
 void Engine::invalidate_graph() {
-  if (gexec || graph) retired_graphs.push_back({graph, gexec});
+  if (gexec || graph) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
+        hipEventRecord(ev, cfg.stream) != hipSuccess) {
+      (void)hipEventDestroy(ev);
+      ev = nullptr;
+    }
+    retired_graphs.push_back({graph, gexec, ev});
+  }
   gexec = nullptr;
   graph = nullptr;
   graph_ok = false;
 }
 
 void Engine::drop_retired_graphs() {
+  std::vector<RetiredGraph> keep;
   for (auto& g : retired_graphs) {
-    if (g.second) (void)hipGraphExecDestroy(g.second);
-    if (g.first) (void)hipGraphDestroy(g.first);
+    if (live && g.after && hipEventQuery(g.after) != hipSuccess) {
+      keep.push_back(g);
+      continue;
+    }
+    if (!g.after) (void)hipStreamSynchronize(cfg.stream);
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    if (g.after) (void)hipEventDestroy(g.after);
   }
-  retired_graphs.clear();
+  retired_graphs.swap(keep);
 }
 
 // ------------------------------------------------------------ boxes
@@ -262,9 +293,17 @@ int Engine::remove_box(int slot) {
   if (slot < 0 || slot >= (int)boxes.size() || !boxes[slot].used) return fail(1, "no such box");
   int rc = set_device();
   if (rc) return rc;
-  HIP_TRY(hipStreamSynchronize(cfg.stream));  // no launch in flight reads its range
-  drop_retired_graphs();
   HostBox& b = boxes[slot];
+  if (b.ready) {
+    // a parked box: every launch that touched it is behind its event
+    HIP_TRY(hipEventSynchronize(b.ready));
+    HIP_TRY(hipStreamSynchronize(copy_stream));
+    (void)hipEventDestroy(b.ready);
+    b.ready = nullptr;
+  } else {
+    HIP_TRY(hipStreamSynchronize(cfg.stream));  // no launch in flight reads its range
+  }
+  drop_retired_graphs();
   long long off = b.off, len = b.reserved;
   // return the range and merge with its neighbours
   auto nx = free_list.lower_bound(off);
@@ -282,7 +321,25 @@ int Engine::remove_box(int slot) {
     }
   }
   free_list[off] = len;
+  const bool was_listed = !b.parked;
   b = HostBox();
+  if (was_listed) {
+    dirty = true;
+    invalidate_graph();
+  }
+  return 0;
+}
+
+// Take a box out of the launches but keep its state readable: its event is
+// recorded behind every launch enqueued so far.
+int Engine::park(int slot) {
+  if (slot < 0 || slot >= (int)boxes.size() || !boxes[slot].used) return fail(1, "no such box");
+  int rc = set_device();
+  if (rc) return rc;
+  HostBox& b = boxes[slot];
+  if (!b.ready) HIP_TRY(hipEventCreateWithFlags(&b.ready, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(b.ready, cfg.stream));
+  b.parked = true;
   dirty = true;
   invalidate_graph();
   return 0;
@@ -452,6 +509,7 @@ int Engine::upload(int slot, const double* cell5, const double* bx, const double
   if ((rc = launch_check())) return rc;
   boxes[slot].have_state = true;
   boxes[slot].cfl_fresh = false;
+  boxes[slot].parked = false;
   if (!dirty && !table_slots.empty()) {
     // the table lists only boxes with a state
     bool listed = std::find(table_slots.begin(), table_slots.end(), slot) != table_slots.end();
@@ -471,8 +529,12 @@ int Engine::download_t(int slot, double* cell5, double* bx, double* by, double* 
   if (rc) return rc;
   const int ppc = (int)std::max<size_t>(1, stage_bytes / plane);
   const int nz = c.n[2] + c.o[2];
-  HIP_TRY(hipEventRecord(compute_ev, cfg.stream));
-  HIP_TRY(hipStreamWaitEvent(copy_stream, compute_ev, 0));
+  if (c.parked && c.ready) {
+    HIP_TRY(hipStreamWaitEvent(copy_stream, c.ready, 0));  // not the launches enqueued since
+  } else {
+    HIP_TRY(hipEventRecord(compute_ev, cfg.stream));
+    HIP_TRY(hipStreamWaitEvent(copy_stream, compute_ev, 0));
+  }
   // chunks in order; chunk i is unpacked while chunk i+1 is copied
   struct Pending {
     int a, k0, k1, idx;
@@ -513,6 +575,17 @@ int Engine::download(int slot, double* cell5, double* bx, double* by, double* bz
   int rc = set_device();
   if (rc) return rc;
   return esize == 8 ? download_t<double>(slot, cell5, bx, by, bz) : download_t<float>(slot, cell5, bx, by, bz);
+}
+
+// A parked box's scalars, read on the copy stream behind its event (not
+// behind the launches enqueued since).
+int Engine::read_scalars_parked(int slot, Scalars* out) {
+  const HostBox& b = boxes[slot];
+  if (!b.parked || !b.ready) return read_scalars(slot, out);
+  HIP_TRY(hipStreamWaitEvent(copy_stream, b.ready, 0));
+  HIP_TRY(hipMemcpyAsync(out, (Scalars*)scal.ptr + slot, sizeof(Scalars), hipMemcpyDeviceToHost, copy_stream));
+  HIP_TRY(hipStreamSynchronize(copy_stream));
+  return 0;
 }
 
 int Engine::read_scalars(int slot, Scalars* out) {
@@ -566,14 +639,14 @@ static long long kind_waves(const HostBox& b, int kind, int target, int groups, 
 }
 
 int Engine::build_lists() {
-  table_slots.clear();
+  std::vector<int> slots;
   for (int s = 0; s < (int)boxes.size(); ++s)
-    if (boxes[s].used && boxes[s].have_state) table_slots.push_back(s);
-  const int nb = (int)table_slots.size();
+    if (boxes[s].used && boxes[s].have_state && !boxes[s].parked) slots.push_back(s);
+  const int nb = (int)slots.size();
   std::vector<BoxDesc> desc(nb);
   std::vector<int> list[K_NUM];
   for (int t = 0; t < nb; ++t) {
-    const HostBox& b = boxes[table_slots[t]];
+    const HostBox& b = boxes[slots[t]];
     BoxDesc& d = desc[t];
     std::memset(&d, 0, sizeof d);
     for (int a = 0; a < 3; ++a) {
@@ -584,7 +657,7 @@ int Engine::build_lists() {
     }
     d.off = b.off;
     d.cfl = b.cfl;
-    d.slot = table_slots[t];
+    d.slot = slots[t];
     for (int k = 0; k < K_NUM; ++k) {
       int par = 1;
       const long long w = kind_waves(b, k, tuning.target[k], tuning.groups[k], &par);
@@ -597,18 +670,50 @@ int Engine::build_lists() {
   }
   int rc = set_device();
   if (rc) return rc;
-  HIP_TRY(hipStreamSynchronize(cfg.stream));  // nothing in flight reads the old lists
+  // the spare set is written once every launch that read it has completed
+  HIP_TRY(hipEventSynchronize(spare.done));
   drop_retired_graphs();
-  if (nb > 0) HIP_TRY(hipMemcpy(table.ptr, desc.data(), sizeof(BoxDesc) * nb, hipMemcpyHostToDevice));
+  size_t total = sizeof(BoxDesc) * (size_t)nb;
+  for (int k = 0; k < K_NUM; ++k) total += list[k].size() * sizeof(int);
+  if (spare.host_bytes < total) {
+    if (spare.host) (void)hipHostFree(spare.host);
+    spare.host = nullptr;
+    spare.host_bytes = 0;
+    const size_t want = total + total / 4 + 4096;
+    HIP_TRY(hipHostMalloc(&spare.host, want, hipHostMallocDefault));
+    spare.host_bytes = want;
+  }
+  char* h = static_cast<char*>(spare.host);
+  if (nb > 0) {
+    std::memcpy(h, desc.data(), sizeof(BoxDesc) * nb);
+    HIP_TRY(hipMemcpyAsync(spare.table.ptr, h, sizeof(BoxDesc) * nb, hipMemcpyHostToDevice, cfg.stream));
+  }
+  h += sizeof(BoxDesc) * nb;
   for (int k = 0; k < K_NUM; ++k) {
     const size_t bytes = list[k].size() * sizeof(int);
-    if (lists[k].bytes < bytes) {
-      dev_free(lists[k]);
-      if ((rc = dev_alloc(lists[k], bytes + bytes / 4))) return rc;
+    if (spare.lists[k].bytes < bytes) {
+      dev_free(spare.lists[k]);
+      if ((rc = dev_alloc(spare.lists[k], bytes + bytes / 4))) return rc;
     }
-    if (bytes) HIP_TRY(hipMemcpy(lists[k].ptr, list[k].data(), bytes, hipMemcpyHostToDevice));
-    nwaves[k] = (int)list[k].size();
+    if (bytes) {
+      std::memcpy(h, list[k].data(), bytes);
+      HIP_TRY(hipMemcpyAsync(spare.lists[k].ptr, h, bytes, hipMemcpyHostToDevice, cfg.stream));
+    }
+    h += bytes;
+    spare.nwaves[k] = (int)list[k].size();
   }
+  spare.slots.swap(slots);
+  // the current set stops being current behind everything enqueued so far
+  HIP_TRY(hipEventRecord(list_done, cfg.stream));
+  std::swap(table, spare.table);
+  for (int k = 0; k < K_NUM; ++k) {
+    std::swap(lists[k], spare.lists[k]);
+    std::swap(nwaves[k], spare.nwaves[k]);
+  }
+  table_slots.swap(spare.slots);
+  std::swap(list_host, spare.host);
+  std::swap(list_host_bytes, spare.host_bytes);
+  std::swap(list_done, spare.done);
   dirty = false;
   invalidate_graph();
   return 0;
@@ -746,6 +851,39 @@ int Engine::launch_check_cfl() {
                        cfg.stream, L);
   }
   return launch_check();
+}
+
+// The CFL speed of boxes just added (their step scalars start at zero): the
+// check kernel over the table without the reset; a box already fresh gets
+// its own value again (the same function of the same state).
+int Engine::check_new() {
+  int rc = ensure_table();
+  if (rc) return rc;
+  if (table_slots.empty()) return 0;
+  if (esize == 8) {
+    CheckLaunch<double> L;
+    for (int k = 0; k < 5; ++k) L.u[k] = (const double*)pool[cur[k]][k].ptr;
+    for (int k = 0; k < 3; ++k) L.b[k] = (const double*)pool[cur[5 + k]][5 + k].ptr;
+    L.gamma = cfg.gamma;
+    L.wl = make_wl(this, K_CHECK);
+    L.sc = (Scalars*)scal.ptr;
+    if (L.wl.nwaves > 0)
+      hipLaunchKernelGGL((check_cfl_kernel<double>), dim3(grid_for((long long)L.wl.nwaves * 64)), dim3(kBlock), 0,
+                         cfg.stream, L);
+  } else {
+    CheckLaunch<float> L;
+    for (int k = 0; k < 5; ++k) L.u[k] = (const float*)pool[cur[k]][k].ptr;
+    for (int k = 0; k < 3; ++k) L.b[k] = (const float*)pool[cur[5 + k]][5 + k].ptr;
+    L.gamma = cfg.gamma;
+    L.wl = make_wl(this, K_CHECK);
+    L.sc = (Scalars*)scal.ptr;
+    if (L.wl.nwaves > 0)
+      hipLaunchKernelGGL((check_cfl_kernel<float>), dim3(grid_for((long long)L.wl.nwaves * 64)), dim3(kBlock), 0,
+                         cfg.stream, L);
+  }
+  if ((rc = launch_check())) return rc;
+  for (int s : table_slots) boxes[s].cfl_fresh = true;
+  return 0;
 }
 
 int Engine::check_cfl_all() {

@@ -10,6 +10,7 @@
 #include <string>
 
 #include "../../include/fish.h"
+#include "batch.h"
 #include "engine.h"
 
 using fish::Engine;
@@ -22,11 +23,6 @@ struct fish_ctx {
   int slot = 0;
 };
 
-struct fish_batch {
-  fish_batch_params p{};
-  Engine e;
-  hipStream_t own_stream = nullptr;
-};
 
 namespace {
 

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/fish.h"
+#include "batch.h"
 #include "engine.h"
 
 using fish::Engine;
@@ -27,7 +28,8 @@ struct fish_server {
     int id;
     int left;
   };
-  std::vector<Resident> resident;
+  std::vector<Resident> resident;   // stepping
+  std::vector<Resident> retiring;   // parked after their last chunk, read at the next call
   std::string err;
   long long steps_done = 0;      // double steps of all boxes, summed
   long long cell_steps = 0;      // cells x double steps, summed
@@ -90,63 +92,69 @@ int fish_server_submit(fish_server* s, const fish_request* r) {
 int fish_server_pump(fish_server* s, int64_t* done_tags, int32_t* done_status, int max_done, int* ndone) {
   if (!s || !ndone || (max_done > 0 && !done_tags)) return s ? sfail(s, FISH_ERR_ARG, "bad output") : FISH_ERR_ARG;
   *ndone = 0;
-  // 1. the next chunk of steps of every resident box, enqueued first so that
-  //    the host work of the admissions below overlaps it; no box overshoots
-  int k = 0;
+  Engine& e = s->batch->e;
+  int rc;
+  // 1. the next chunk of every stepping box (asynchronous); no box overshoots.
+  //    Boxes done after it leave the launches at once (parked behind it) and
+  //    are read at the next call, while the following chunk runs.
+  std::vector<fish_server::Resident> finishing;
   if (!s->resident.empty()) {
-    k = s->chunk;
+    int k = s->chunk;
     for (const auto& x : s->resident) k = std::min(k, x.left);
-    int rc = fish_batch_step(s->batch, k);
-    if (rc) return sfail(s, rc, fish_batch_last_error(s->batch));
-  }
-  const size_t stepped = s->resident.size();
-  // 2. admission in arrival order while the head fits (no overtaking); the
-  //    new boxes take no step of this chunk
-  while (!s->queue.empty()) {
-    const fish_request& r = s->queue.front();
-    int id = -1;
-    int rc = fish_batch_add(s->batch, &r.box, r.cell5, r.bx, r.by, r.bz, r.phi, &id);
-    if (rc == FISH_ERR_NOMEM) break;  // wait for a retirement
-    if (rc != FISH_OK) {
-      // a request whose state fails the check completes at once with its status
-      if (*ndone >= max_done) return sfail(s, FISH_ERR_ARG, "done buffer too small");
-      done_tags[*ndone] = r.tag;
-      if (done_status) done_status[*ndone] = rc;
-      ++*ndone;
-      s->queue.pop_front();
-      continue;
+    if ((rc = e.steps(k))) return sfail(s, rc, e.err);
+    std::vector<fish_server::Resident> keep;
+    for (auto& x : s->resident) {
+      x.left -= k;
+      s->cell_steps += (long long)k * x.req.box.nx * x.req.box.ny * x.req.box.nz;
+      if (x.left > 0) {
+        keep.push_back(x);
+      } else {
+        if ((rc = e.park(x.id))) return sfail(s, rc, e.err);
+        finishing.push_back(x);
+      }
     }
-    s->resident.push_back({r, id, r.nsteps});
-    s->queue.pop_front();
+    s->resident.swap(keep);
+    s->steps_done += k;
   }
-  for (size_t i = 0; i < stepped; ++i) {
-    auto& x = s->resident[i];
-    x.left -= k;
-    s->cell_steps += (long long)k * x.req.box.nx * x.req.box.ny * x.req.box.nz;
-  }
-  s->steps_done += k;
-  // 3. retire finished boxes (their downloads wait for the chunk)
-  std::vector<fish_server::Resident> keep;
-  keep.reserve(s->resident.size());
-  for (auto& x : s->resident) {
-    if (x.left > 0) {
-      keep.push_back(x);
-      continue;
-    }
+  // 2. retire the boxes parked by the previous call: their reads wait for the
+  //    chunk that finished them, not for the one just enqueued
+  std::vector<fish_server::Resident> later;
+  for (auto& x : s->retiring) {
     if (*ndone >= max_done) {
-      keep.push_back(x);  // report it at the next pump
+      later.push_back(x);  // report it at the next call
       continue;
     }
-    double t = 0.0;
-    int st = fish_batch_get(s->batch, x.id, x.req.out_cell5, x.req.out_bx, x.req.out_by, x.req.out_bz, &t);
-    if (st != FISH_OK && st != FISH_ERR_STATE) return sfail(s, st, fish_batch_last_error(s->batch));
-    int rc = fish_batch_remove(s->batch, x.id);
-    if (rc) return sfail(s, rc, fish_batch_last_error(s->batch));
+    fish::Scalars sc;
+    if ((rc = e.read_scalars_parked(x.id, &sc))) return sfail(s, rc, e.err);
+    if ((rc = e.download(x.id, x.req.out_cell5, x.req.out_bx, x.req.out_by, x.req.out_bz)))
+      return sfail(s, rc, e.err);
+    if ((rc = e.remove_box(x.id))) return sfail(s, rc, e.err);
     done_tags[*ndone] = x.req.tag;
-    if (done_status) done_status[*ndone] = st;
+    if (done_status) done_status[*ndone] = sc.status ? FISH_ERR_STATE : FISH_OK;
     ++*ndone;
   }
-  s->resident.swap(keep);
+  s->retiring.swap(later);
+  s->retiring.insert(s->retiring.end(), finishing.begin(), finishing.end());
+  // 3. admission in arrival order while the head fits (no overtaking): host
+  //    repacking and the copies overlap the chunk; the CFL check runs behind
+  //    it.  A state that fails the check stops (dt = 0) and completes with
+  //    FISH_ERR_STATE.
+  bool added = false;
+  while (!s->queue.empty()) {
+    const fish_request& r = s->queue.front();
+    const int n[3] = {r.box.nx, r.box.ny, r.box.nz};
+    const double h[3] = {r.box.dx, r.box.dy, r.box.dz};
+    const int bc[3] = {r.box.bc[0], r.box.bc[1], r.box.bc[2]};
+    int id = -1;
+    rc = e.add_box(n, h, bc, r.box.cfl, &id);
+    if (rc == FISH_ERR_NOMEM) break;  // wait for a retirement
+    if (rc) return sfail(s, rc, e.err);
+    if ((rc = e.upload(id, r.cell5, r.bx, r.by, r.bz, r.phi))) return sfail(s, rc, e.err);
+    s->resident.push_back({r, id, r.nsteps});
+    s->queue.pop_front();
+    added = true;
+  }
+  if (added && (rc = e.check_new())) return sfail(s, rc, e.err);
   return FISH_OK;
 }
 
