@@ -67,7 +67,7 @@ def run_gpu(fish, torch, st, n, precision, steps, warmup, cfl, segment, autotune
     after it stops, so every timed step advances a physically valid state."""
     box = fish.Box(*n, precision=precision, cfl=cfl)
     box.set_state(st)
-    tuned = box.autotune(reps=3) if autotune else None
+    tuned = box.autotune(reps=5) if autotune else None
     for _ in range(warmup):
         box.strang_step(0.0)
     torch.cuda.synchronize()
