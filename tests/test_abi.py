@@ -41,3 +41,45 @@ def test_create_rejects_bad_arguments_without_touching_a_device():
     assert not h.value
     assert lib.fish_create(None, ctypes.byref(h)) == fish.FISH_ERR_ARG
     lib.fish_destroy(None)
+
+
+def _valid_params(n, precision):
+    p = fish.Params()
+    p.nx, p.ny, p.nz = n
+    p.dx, p.dy, p.dz = (1.0 / v for v in n)
+    p.gamma, p.cfl = 5.0 / 3.0, 0.5
+    p.limiter = fish.VANLEER
+    p.predictor_alpha = 1.0
+    p.precision = precision
+    return p
+
+
+def test_create_rejects_arrays_beyond_32bit_offsets_without_touching_a_device():
+    """Each array of a box must stay below 4 GiB (the kernels address it with
+    32-bit byte offsets): 1100^3 in FP32 is refused before any HIP call."""
+    lib = fish.load_library()
+    h = ctypes.c_void_p()
+    assert lib.fish_create(ctypes.byref(_valid_params((1100, 1100, 1100), fish.FP32)), ctypes.byref(h)) == \
+        fish.FISH_ERR_UNSUPPORTED
+    assert not h.value
+    # FP64 doubles the bytes per array: refused as well
+    assert lib.fish_create(ctypes.byref(_valid_params((1100, 1100, 1100), fish.FP64)), ctypes.byref(h)) == \
+        fish.FISH_ERR_UNSUPPORTED
+
+
+def test_batch_and_box_geometry_checks_without_a_device():
+    lib = fish.load_library()
+    g = fish.BoxGeom()
+    g.nx, g.ny, g.nz = 16, 16, 16
+    g.dx = g.dy = g.dz = 1.0 / 16
+    g.cfl = 0.5
+    # both buffers of 8 arrays, padded to 64 elements
+    assert lib.fish_box_pool_bytes(ctypes.byref(g), fish.FP32, 0) == 16 * 4096 * 4
+    assert lib.fish_box_pool_bytes(ctypes.byref(g), fish.FP64, 1) == 17 * 4096 * 8
+    bp = fish.BatchParams()
+    bp.gamma, bp.limiter, bp.predictor_alpha, bp.precision = 5.0 / 3.0, fish.VANLEER, 1.0, fish.FP32
+    bp.max_boxes = 0  # invalid: rejected before any HIP call
+    bp.pool_bytes = 1 << 20
+    h = ctypes.c_void_p()
+    assert lib.fish_batch_create(ctypes.byref(bp), ctypes.byref(h)) == fish.FISH_ERR_ARG
+    assert not h.value

@@ -211,3 +211,19 @@ def test_batch_rejects_a_bad_box_and_keeps_the_rest():
     for k in FIELDS:
         assert np.array_equal(got[k], ref[k]), k
     b.close()
+
+
+def test_empty_batch_and_server():
+    import paper_0910_2854_amd as fish
+    print("empty batch and server", flush=True)
+    b = _batch("fp32")
+    b.step(3)  # no boxes: nothing to do
+    b.sync()
+    assert len(b) == 0
+    with pytest.raises(fish.FishError):
+        b.autotune(reps=1)  # nothing to tune on
+    b.close()
+    srv = fish.Server(16 << 20, precision="fp32")
+    assert srv.pump() == []
+    assert srv.stats()["resident"] == 0
+    srv.close()
