@@ -35,7 +35,8 @@ import numpy as np
 __all__ = [
     "empty_state", "conserved_from_primitive", "cell_centred_b", "curl_of_potential",
     "random_fourier_state", "sphere_state", "uniform_state", "kvectors", "batch_box_specs",
-    "serving_requests",
+    "serving_requests", "sedov_state", "spherical_riemann_state", "magnetic_explosion_state", "rotor_state",
+    "mhd_riemann_2d_state",
 ]
 
 
@@ -260,3 +261,119 @@ def serving_requests(nreq, rate, seed=7, edge_range=(32, 192), step_range=(10, 2
         steps = int(rng.integers(step_range[0], step_range[1] + 1))
         out.append({"arrival": t, "edge": edge, "steps": steps, "seed": 100000 + r})
     return out
+
+
+# ---------------------------------------------------------------------------
+# Initial states of the paper's validation problems (Sect. 4.2-4.6).  Every
+# field is sampled at cell centres (faces for b); a cell belongs to a region
+# when its centre does.  Each builder returns (state, setup) where setup holds
+# the box shape, spacings, gamma, boundaries, limiter, CFL number and end time
+# that the section states (or the reading taken where it states none).
+
+PERIODIC_BC, OUTFLOW_BC = 0, 1
+MINMOD_LIMITER, VANLEER_LIMITER = 0, 1
+
+
+def _centres(n, L=1.0):
+    return (np.arange(n) + 0.5) * (L / n)
+
+
+def _radius_from_centre(n, L=(1.0, 1.0, 1.0)):
+    nx, ny, nz = n
+    x = _centres(nx, L[0]) - 0.5 * L[0]
+    y = _centres(ny, L[1]) - 0.5 * L[1]
+    z = _centres(nz, L[2]) - 0.5 * L[2]
+    return np.sqrt(z[:, None, None] ** 2 + y[None, :, None] ** 2 + x[None, None, :] ** 2)
+
+
+def _setup(n, L, gamma, bc, limiter, cfl, t_end):
+    return {"shape": tuple(int(v) for v in n), "h": tuple(L[a] / n[a] for a in range(3)), "L": tuple(L),
+            "gamma": gamma, "bc": tuple(bc), "limiter": limiter, "cfl": cfl, "t_end": t_end}
+
+
+def sedov_state(n=256, e_in=3.0e3, e_out=1.0e-3, r_dep=0.01, gamma=5.0 / 3.0):
+    """Sedov-Taylor blast (Sect. 4.2): unit cube, rho = 1, v = 0, internal
+    energy per volume e_in inside r < r_dep around the centre and e_out outside,
+    b = 0.  The end time is left to the caller (the section's stop time and
+    shock radius do not agree with each other)."""
+    N = (n, n, n)
+    r = _radius_from_centre(N)
+    e = np.where(r < r_dep, e_in, e_out)
+    one = np.ones_like(r)
+    zero = 0.0 * one
+    st = conserved_from_primitive(one, zero, zero, zero, (gamma - 1.0) * e, np.zeros((n, n, n + 1)),
+                                  np.zeros((n, n + 1, n)), np.zeros((n + 1, n, n)), gamma)
+    return st, _setup(N, (1.0,) * 3, gamma, (PERIODIC_BC,) * 3, VANLEER_LIMITER, 0.5, None)
+
+
+def spherical_riemann_state(n=256, gamma=5.0 / 3.0):
+    """Spherical Riemann problem (Sect. 4.3): unit cube, v = 0, b = 0;
+    rho = 0.125, p = 0.1 inside r < 0.25 around the centre, rho = 1, p = 1
+    outside; t = 0.09."""
+    N = (n, n, n)
+    r = _radius_from_centre(N)
+    inside = r < 0.25
+    rho = np.where(inside, 0.125, 1.0)
+    p = np.where(inside, 0.1, 1.0)
+    zero = 0.0 * rho
+    st = conserved_from_primitive(rho, zero, zero, zero, p, np.zeros((n, n, n + 1)), np.zeros((n, n + 1, n)),
+                                  np.zeros((n + 1, n, n)), gamma)
+    return st, _setup(N, (1.0,) * 3, gamma, (OUTFLOW_BC,) * 3, VANLEER_LIMITER, 0.5, 0.09)
+
+
+def magnetic_explosion_state(n=256, gamma=5.0 / 3.0):
+    """Magnetic explosion (Sect. 4.4): unit cube, rho = 1, v = 0; p = 100 for
+    r < 0.1, p = 1 for r > 0.125, linear in r between; b = (7, 7, 0)/sqrt(2);
+    minmod limiter, CFL 0.5, t = 0.03."""
+    N = (n, n, n)
+    r = _radius_from_centre(N)
+    p = np.where(r < 0.1, 100.0, np.where(r < 0.125, 100.0 + (1.0 - 100.0) * (r - 0.1) / 0.025, 1.0))
+    one = np.ones_like(r)
+    zero = 0.0 * one
+    b0 = 7.0 / math.sqrt(2.0)
+    st = conserved_from_primitive(one, zero, zero, zero, p, np.full((n, n, n + 1), b0), np.full((n, n + 1, n), b0),
+                                  np.zeros((n + 1, n, n)), gamma)
+    return st, _setup(N, (1.0,) * 3, gamma, (OUTFLOW_BC,) * 3, MINMOD_LIMITER, 0.5, 0.03)
+
+
+def rotor_state(n=256, gamma=1.4):
+    """Rotor (Sect. 4.5): unit square, one cell along z.  rho = 10 spinning
+    at angular speed 2/r0 inside r0 = 0.1, resting rho = 1 beyond r1 = 0.115,
+    the taper f = (r1 - r)/(r1 - r0) between; p = 1, b = (5/sqrt(4 pi), 0, 0),
+    gamma = 1.4, t = 0.15."""
+    x = _centres(n)
+    X = x[None, None, :] - 0.5
+    Y = x[None, :, None] - 0.5
+    r = np.sqrt(X * X + Y * Y)
+    r0, r1 = 0.1, 0.115
+    f = (r1 - r) / (r1 - r0)
+    rho = np.where(r < r0, 10.0, np.where(r < r1, 1.0 + 9.0 * f, 1.0))
+    w = np.where(r < r0, 2.0 / r0, np.where(r < r1, 2.0 * f / np.maximum(r, 1e-300), 0.0))
+    vx = -w * Y
+    vy = w * X
+    one = np.ones((1, n, n))
+    st = conserved_from_primitive(rho * one, vx * one, vy * one, 0.0 * one, one,
+                                  np.full((1, n, n + 1), 5.0 / math.sqrt(4.0 * math.pi)), np.zeros((1, n + 1, n)),
+                                  np.zeros((2, n, n)), gamma)
+    return st, _setup((n, n, 1), (1.0, 1.0, 1.0 / n), gamma, (OUTFLOW_BC, OUTFLOW_BC, PERIODIC_BC),
+                      VANLEER_LIMITER, 0.5, 0.15)
+
+
+def mhd_riemann_2d_state(n=512, gamma=5.0 / 3.0, L=0.8):
+    """Two-dimensional MHD Riemann problem (Sect. 4.6): [0, 0.8]^2, one cell
+    along z, four constant quadrants (rho, v_x, v_y) = (1, -0.75, 0.5) lower
+    left, (3, -0.75, -0.5) lower right, (2, 0.75, 0.5) upper left,
+    (1, 0.75, -0.5) upper right, v_z = 0, p = 1; b = (2, 0, 1)/sqrt(4 pi);
+    zeroth-order extrapolation (outflow) boundaries; t = 0.8."""
+    x = _centres(n, L)
+    lx = (x <= 0.5 * L)[None, None, :]
+    ly = (x <= 0.5 * L)[None, :, None]
+    rho = np.where(ly, np.where(lx, 1.0, 3.0), np.where(lx, 2.0, 1.0))
+    vx = np.where(ly, -0.75, 0.75) * np.ones_like(rho)
+    vy = np.where(ly, np.where(lx, 0.5, -0.5), np.where(lx, 0.5, -0.5))
+    one = np.ones((1, n, n))
+    s4 = math.sqrt(4.0 * math.pi)
+    st = conserved_from_primitive(rho * one, vx * one, vy * one, 0.0 * one, one, np.full((1, n, n + 1), 2.0 / s4),
+                                  np.zeros((1, n + 1, n)), np.full((2, n, n), 1.0 / s4), gamma)
+    return st, _setup((n, n, 1), (L, L, L / n), gamma, (OUTFLOW_BC, OUTFLOW_BC, PERIODIC_BC), VANLEER_LIMITER, 0.5,
+                      0.8)

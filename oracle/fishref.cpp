@@ -395,9 +395,13 @@ void field_row(const std::vector<double>& w, const std::vector<double>& b, int n
                int limiter, std::vector<double>& bnew, std::vector<double>& emf) {
   const int M = n + 2 * G;
   auto lim = [&](double a, double c) { return limiter == 0 ? minmod(a, c) : vanleer(a, c); };
-  // 1-2-1 smoothing of the face velocity along d, Eq. (66).
+  // 1-2-1 smoothing of the face velocity along d, Eq. (66).  reading: the two
+  // outer neighbours are summed first, so that a face velocity odd about an
+  // interface gives smoothed velocities that are exact negatives of each
+  // other there and an interface velocity of exactly zero, which the <= 0
+  // branch of Eq. (67) then decides (rounding cannot pick the branch).
   std::vector<double> vb(M, 0.0);
-  for (int m = 1; m < M - 1; ++m) vb[m] = 0.25 * (w[m - 1] + 2.0 * w[m] + w[m + 1]);
+  for (int m = 1; m < M - 1; ++m) vb[m] = 0.25 * ((w[m - 1] + w[m + 1]) + 2.0 * w[m]);
   // Interface velocity, Eq. (68), and cell flux v b.
   std::vector<double> V(M, 0.0), f(M, 0.0);
   for (int m = 1; m < M - 2; ++m) V[m] = 0.5 * (vb[m] + vb[m + 1]);

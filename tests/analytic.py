@@ -283,3 +283,110 @@ def rh_downstream(WR, s, gamma, guess):
     if ier != 1:
         raise RuntimeError(msg)
     return sol, float(np.max(np.abs(res(sol))))
+
+
+# ------------------------------------ radial Euler reference (1-D, spherical)
+def _minmod(a, b):
+    return np.where(a * b > 0.0, np.sign(a) * np.minimum(np.abs(a), np.abs(b)), 0.0)
+
+
+def _hlle_flux(WL, WR, gamma):
+    def cons_flux(W):
+        rho, u, p = W
+        E = p / (gamma - 1.0) + 0.5 * rho * u * u
+        return np.stack([rho, rho * u, E]), np.stack([rho * u, rho * u * u + p, (E + p) * u])
+
+    UL, FL = cons_flux(WL)
+    UR, FR = cons_flux(WR)
+    cL = np.sqrt(gamma * WL[2] / WL[0])
+    cR = np.sqrt(gamma * WR[2] / WR[0])
+    SL = np.minimum(np.minimum(WL[1] - cL, WR[1] - cR), 0.0)
+    SR = np.maximum(np.maximum(WL[1] + cL, WR[1] + cR), 0.0)
+    return (SR * FL - SL * FR + SL * SR * (UR - UL)) / (SR - SL)
+
+
+def euler_radial(rho, u, p, dr, gamma, t_end, geometry=2, cfl=0.4, inner="reflect"):
+    """Euler equations in one radial coordinate, a textbook finite-volume
+    scheme of its own (not the FISH scheme): MUSCL reconstruction of the
+    primitive variables with minmod slopes, the HLLE flux, Heun (RK2) steps.
+
+    geometry 0 is planar, 2 spherical: faces r_f = f dr carry the area
+    r_f^geometry, cells the volume (r_{i+1}^(g+1) - r_i^(g+1))/(g+1), and the
+    momentum gains p_i (A_{i+1} - A_i)/V_i, the pressure on the side walls of
+    the cone, so that a uniform pressure at rest stays at rest.  The inner end
+    reflects (r = 0, or a wall) or lets waves out; the outer end lets them out
+    (zeroth-order extrapolation).  Returns (rho, u, p) at the cell centres."""
+    g = gamma
+    n = len(rho)
+    rf = np.arange(n + 1) * dr
+    A = rf ** geometry
+    V = (rf[1:] ** (geometry + 1) - rf[:-1] ** (geometry + 1)) / (geometry + 1)
+    dA = A[1:] - A[:-1]
+
+    def prim(U):
+        r = U[0]
+        v = U[1] / r
+        return np.stack([r, v, (g - 1.0) * (U[2] - 0.5 * r * v * v)])
+
+    def rhs(U):
+        W = prim(U)
+        Wg = np.empty((3, n + 4))
+        Wg[:, 2:-2] = W
+        if inner == "reflect":
+            Wg[:, 1], Wg[:, 0] = W[:, 0], W[:, 1]
+            Wg[1, :2] *= -1.0
+        else:
+            Wg[:, 0] = Wg[:, 1] = W[:, 0]
+        Wg[:, -2] = Wg[:, -1] = W[:, -1]
+        d = np.diff(Wg, axis=1)
+        slope = _minmod(d[:, :-1], d[:, 1:])
+        F = _hlle_flux(Wg[:, 1:-2] + 0.5 * slope[:, :-1], Wg[:, 2:-1] - 0.5 * slope[:, 1:], g)
+        dU = -(A[1:] * F[:, 1:] - A[:-1] * F[:, :-1]) / V
+        dU[1] += W[2] * dA / V
+        return dU, W
+
+    U = np.stack([rho, rho * u, p / (g - 1.0) + 0.5 * rho * u * u]).astype(np.float64)
+    t = 0.0
+    while t < t_end * (1.0 - 1e-12):
+        dU, W = rhs(U)
+        smax = float(np.max(np.abs(W[1]) + np.sqrt(g * W[2] / W[0])))
+        dt = min(cfl * dr / smax, t_end - t)
+        U1 = U + dt * dU
+        U = 0.5 * (U + U1 + dt * rhs(U1)[0])
+        t += dt
+    return tuple(prim(U))
+
+
+# ------------------------------------------------ Sedov-Taylor similarity law
+# Radius of a strong point blast of energy E in gas of density rho:
+# R = xi0 (E t^2 / rho)^(1/5) (dimensional analysis fixes the exponent);
+# xi0 = 1.152 for gamma = 5/3 from the similarity solution (Sedov; Landau &
+# Lifshitz, Fluid Mechanics, Sect. 106).
+SEDOV_XI0_GAMMA_5_3 = 1.152
+
+
+def sedov_radius(E, t, rho=1.0, xi0=SEDOV_XI0_GAMMA_5_3):
+    return xi0 * (E * t * t / rho) ** 0.2
+
+
+def radial_bins(field, r, h, rmax):
+    """Mean of a cell field in radial shells of width h (shell k: k h <= r < (k+1) h)."""
+    k = np.floor(r / h).astype(np.int64).ravel()
+    nb = int(rmax / h)
+    sel = k < nb
+    s = np.bincount(k[sel], weights=field.ravel()[sel], minlength=nb)
+    c = np.bincount(k[sel], minlength=nb)
+    centres = (np.arange(nb) + 0.5) * h
+    return centres[c > 0], s[c > 0] / c[c > 0]
+
+
+def shock_radius(rc, prof, ambient):
+    """Outermost radius where a radial profile falls through the midpoint
+    between its peak and the ambient value (linear between shells)."""
+    level = ambient + 0.5 * (float(np.max(prof)) - ambient)
+    above = np.where(prof > level)[0]
+    i = int(above[-1])
+    if i + 1 >= len(prof):
+        return float(rc[i])
+    f = (prof[i] - level) / (prof[i] - prof[i + 1])
+    return float(rc[i] + f * (rc[i + 1] - rc[i]))
