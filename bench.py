@@ -108,11 +108,11 @@ def pct(sorted_vals, q):
     return sorted_vals[k]
 
 
-def cpu_baseline(st, n, cfl, steps):
+def cpu_baseline(st, n, cfl, steps, **kw):
     from oracle import Oracle
 
     cores = len(os.sched_getaffinity(0))
-    o = Oracle(*n, cfl=cfl, nthreads=cores)
+    o = Oracle(*n, cfl=cfl, nthreads=cores, **kw)
     o.set_state(st)
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -395,6 +395,93 @@ def bench_sphere(args, torch, fish, fi):
     print(json.dumps(out), flush=True)
 
 
+PROBLEMS = (
+    ("sedov", "Sedov-Taylor blast 256^3 (Sect. 4.2), until the shock reaches r = 0.45"),
+    ("spherical_riemann", "spherical Riemann problem 256^3 (Sect. 4.3), t = 0.09"),
+    ("magnetic_explosion", "magnetic explosion 256^3 (Sect. 4.4), minmod, t = 0.03"),
+    ("rotor", "rotor 256^2 (Sect. 4.5), t = 0.15"),
+    ("mhd_riemann_2d", "2-D MHD Riemann problem 512^2 (Sect. 4.6), t = 0.8"),
+)
+
+
+def _problem_state(fi, name):
+    if name == "sedov":
+        st, s = fi.sedov_state(256)
+        h = s["h"][0]
+        eb = (float(st["cell"][4].sum()) - 1e-3 * st["cell"][4].size) * h ** 3
+        s["t_end"] = (0.45 / 1.152) ** 2.5 / math.sqrt(eb)  # similarity law R = 1.152 (E t^2/rho)^(1/5)
+        return st, s
+    return {"spherical_riemann": fi.spherical_riemann_state, "magnetic_explosion": fi.magnetic_explosion_state,
+            "rotor": fi.rotor_state, "mhd_riemann_2d": fi.mhd_riemann_2d_state}[name]()
+
+
+def bench_problems(args, torch, fish, fi):
+    """The validation problems of Sect. 4.2-4.6 at the paper's sizes, FP32,
+    each run to its end time from a state resident on the GPU: every step
+    reads the device CFL step, shortens the last one to land on the end time
+    and runs the twelve sub-operators."""
+    total_cells, total_wall, total_steps, per, roof = 0, 0.0, 0, {}, None
+    for name, desc in PROBLEMS:
+        st, s = _problem_state(fi, name)
+        h = s["h"]
+        box = fish.Box(*s["shape"], dx=h[0], dy=h[1], dz=h[2], gamma=s["gamma"], cfl=s["cfl"], limiter=s["limiter"],
+                       bc=s["bc"], precision="fp32")
+        box.set_state(st)
+        ncell = s["shape"][0] * s["shape"][1] * s["shape"][2]
+        log(f"{name}: {s['shape']} to t = {s['t_end']:.4f}")
+        timed = name == "magnetic_explosion"
+        if timed:
+            box.timing_enable(fish.KERNEL_FLUID, max_launches=6 * 400)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t, k = 0.0, 0
+        while t < s["t_end"] - 1e-14:
+            dt = min(box.cfl_dt(), 0.5 * (s["t_end"] - t))
+            box.strang_step(dt)
+            t += 2.0 * dt
+            k += 1
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if timed:
+            launches, fluid_ms = box.timing_read()
+            avg_s = fluid_ms / max(1, launches) * 1e-3
+            b = ncell * 13 * 4
+            roof = {"bound": "hbm", "achieved": b / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": b / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                    "kernel": "fluid sweep (L_x, L_y, L_z), magnetic explosion 256^3, minmod",
+                    "avg_launch_ms": avg_s * 1e3, "launches": launches, "algorithmic_bytes_per_launch": b}
+        x = box.get_state()
+        box.close()
+        c = x["cell"]
+        ke = 0.5 * (c[1] ** 2 + c[2] ** 2 + c[3] ** 2) / c[0]
+        bc = fi.cell_centred_b(x["bx"], x["by"], x["bz"])
+        me = 0.5 * (bc[0] ** 2 + bc[1] ** 2 + bc[2] ** 2)
+        p = (s["gamma"] - 1.0) * (c[4] - ke - me)
+        per[name] = {"problem": desc, "cells": ncell, "steps": k, "wall_s": wall,
+                     "value": ncell * k / wall, "ms_per_step": wall * 1e3 / k,
+                     "ranges": {"rho": [float(c[0].min()), float(c[0].max())], "p": [float(p.min()), float(p.max())],
+                                "e_mag": [float(me.min()), float(me.max())], "e_kin": [float(ke.min()), float(ke.max())]}}
+        log(f"  {k} steps, {wall:.2f} s, {ncell * k / wall:.3e} cell-updates/s")
+        total_cells += ncell * k
+        total_wall += wall
+        total_steps += k
+        del st, x
+    out = {
+        "metric": METRIC, "value": total_cells / total_wall, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": total_steps, "warmup": 0, "ms_per_step": total_wall * 1e3 / total_steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "the validation problems of Sect. 4.2-4.6 at the paper's sizes, each from its "
+                               "initial state to its end time, host-read CFL step per step, FP32 with FP64 "
+                               "pressure recovery", "problems": per},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        st, s = _problem_state(fi, "magnetic_explosion")
+        log(f"CPU oracle baseline: {args.cpu_steps} step(s) of the magnetic explosion")
+        out["cpu_baseline"] = cpu_baseline(st, s["shape"], s["cfl"], args.cpu_steps, limiter=s["limiter"], bc=s["bc"])
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -410,8 +497,9 @@ def main():
                          "box loses positivity after 6 steps, in the oracle as well)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration)")
-    ap.add_argument("--workload", choices=("box", "batch", "serve", "sphere"), default="box",
-                    help="box: the 256^3 box (default); batch: 2048 boxes of uneven size; serve: request loop")
+    ap.add_argument("--workload", choices=("box", "batch", "serve", "sphere", "problems"), default="box",
+                    help="box: the 256^3 box (default); batch: 2048 boxes of uneven size; serve: request loop; "
+                         "sphere: 512^3 sphere with gravity + HSE; problems: the validation problems of Sect. 4.2-4.6")
     ap.add_argument("--boxes", type=int, default=2048)
     ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
     ap.add_argument("--single-sample", type=int, default=8, help="boxes per size for the single-box comparison")
@@ -449,6 +537,8 @@ def main():
         return bench_serve(args, torch, fish, fi)
     if args.workload == "sphere":
         return bench_sphere(args, torch, fish, fi)
+    if args.workload == "problems":
+        return bench_problems(args, torch, fish, fi)
     n = (args.n,) * 3
     ncell = n[0] * n[1] * n[2]
     cfl = 0.5

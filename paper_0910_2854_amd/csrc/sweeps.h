@@ -748,7 +748,9 @@ __device__ __forceinline__ T row_position(T w0, T bb, T b4_loaded, T k_half, T k
                                           RowHist<T>& ho, T& bn) {
   const T w1 = H::prev(w0, hi.w1, ho.w1);
   const T w2 = H::prev(w1, hi.w2, ho.w2);
-  const T vbc = T(0.25) * (w2 + T(2) * w1 + w0);   // v-bar of c-1
+  // outer neighbours first: an odd face velocity gives exact negatives here
+  // and V = 0 exactly, which the <= 0 branch of Eq. (67) decides
+  const T vbc = T(0.25) * ((w2 + w0) + T(2) * w1);   // v-bar of c-1
   const T b1 = H::prev(bb, hi.b1, ho.b1);                   // b of c-1
   const T fc = vbc * b1;                            // f of c-1
   const T vb1 = H::prev(vbc, hi.vb1, ho.vb1);                // v-bar of c-2
@@ -1108,7 +1110,7 @@ __device__ __forceinline__ void row_position2(const T (&w0)[2], const T (&bb)[2]
   prev2(w0, w1, h.w1);
   prev2(w1, w2, h.w2);
 #pragma unroll
-  for (int j = 0; j < 2; ++j) vbc[j] = T(0.25) * (w2[j] + T(2) * w1[j] + w0[j]);  // v-bar of c-1
+  for (int j = 0; j < 2; ++j) vbc[j] = T(0.25) * ((w2[j] + w0[j]) + T(2) * w1[j]);  // v-bar of c-1 (as above)
   prev2(bb, b1, h.b1);
 #pragma unroll
   for (int j = 0; j < 2; ++j) fc[j] = vbc[j] * b1[j];
