@@ -377,3 +377,82 @@ def mhd_riemann_2d_state(n=512, gamma=5.0 / 3.0, L=0.8):
                                   np.zeros((1, n + 1, n)), np.full((2, n, n), 1.0 / s4), gamma)
     return st, _setup((n, n, 1), (L, L, L / n), gamma, (OUTFLOW_BC, OUTFLOW_BC, PERIODIC_BC), VANLEER_LIMITER, 0.5,
                       0.8)
+
+
+def lane_emden(n_index=3.0, xi_max=20.0):
+    """Lane-Emden solution theta(xi) of index n: theta'' + 2 theta'/xi +
+    theta^n = 0, theta(0) = 1, theta'(0) = 0, integrated (from a series start
+    at xi = 1e-4) to its first zero xi1.  Returns (theta, xi1, dtheta_xi1) with
+    theta a callable that is 0 beyond xi1."""
+    from scipy.integrate import solve_ivp
+
+    n = float(n_index)
+    x0 = 1e-4
+    y0 = [1.0 - x0 ** 2 / 6.0 + n * x0 ** 4 / 120.0, -x0 / 3.0 + n * x0 ** 3 / 30.0]
+
+    def rhs(x, y):
+        th = max(y[0], 0.0)
+        return [y[1], -th ** n - 2.0 * y[1] / x]
+
+    def surface(x, y):
+        return y[0]
+    surface.terminal = True
+    surface.direction = -1
+    sol = solve_ivp(rhs, (x0, xi_max), y0, events=surface, dense_output=True, rtol=1e-12, atol=1e-14,
+                    method="DOP853")
+    xi1 = float(sol.t_events[0][0])
+    dth1 = float(sol.y_events[0][0][1])
+
+    def theta(xi):
+        xi = np.asarray(xi, dtype=np.float64)
+        out = np.zeros_like(xi)
+        inner = xi < x0
+        mid = (~inner) & (xi < xi1)
+        out[inner] = 1.0 - xi[inner] ** 2 / 6.0
+        if np.any(mid):
+            out[mid] = np.maximum(sol.sol(xi[mid])[0], 0.0)
+        return out
+
+    return theta, xi1, dth1
+
+
+def polytrope_model(M=1.0, R=1.0, G=1.0, n_index=3.0):
+    """Polytropic star p = kappa rho^(1+1/n) of mass M and radius R
+    (Sect. 4.7): central density, kappa, mean density, the length scale alpha
+    = R/xi1, and the hydrostatic time scale (rho_mean G)^(-1/2)/2."""
+    theta, xi1, dth1 = lane_emden(n_index)
+    alpha = R / xi1
+    rho_c = M * xi1 / (4.0 * math.pi * R ** 3 * (-dth1))
+    kappa = 4.0 * math.pi * G * alpha ** 2 * rho_c ** (1.0 - 1.0 / n_index) / (n_index + 1.0)
+    rho_mean = M / (4.0 / 3.0 * math.pi * R ** 3)
+    return {"theta": theta, "xi1": xi1, "dtheta_xi1": dth1, "alpha": alpha, "rho_c": rho_c, "kappa": kappa,
+            "rho_mean": rho_mean, "tau_hse": 0.5 / math.sqrt(rho_mean * G), "n": n_index, "M": M, "R": R, "G": G}
+
+
+def polytrope_state(n=64, L=2.9, atmosphere=1e-6, gamma=4.0 / 3.0, virial_atmosphere=True):
+    """Steady polytrope (Sect. 4.7) in units G = M = R = 1: an n = 3 star
+    centred in [0, L]^3; rho = rho_c theta^3 inside R, a resting atmosphere of
+    rho_atm = atmosphere * rho_c outside; p = kappa rho^(4/3), but at least
+    rho_atm G M / R (the atmosphere at the virial temperature, not in
+    equilibrium; a colder one falls in supersonically and a total-energy
+    scheme then recovers negative pressures within half a tau_HSE); the fixed
+    potential -M/R - 4 kappa rho_c^(1/3) theta inside and -M/r outside; v = 0,
+    b = 0; gas gamma 4/3; outflow boundaries."""
+    mod = polytrope_model()
+    N = (n, n, n)
+    r = _radius_from_centre(N, (L, L, L))
+    th = mod["theta"](r / mod["alpha"])
+    inside = r < mod["R"]
+    rho = np.where(inside, mod["rho_c"] * th ** 3, atmosphere * mod["rho_c"])
+    rho = np.maximum(rho, atmosphere * mod["rho_c"])
+    p = mod["kappa"] * rho ** (4.0 / 3.0)
+    if virial_atmosphere:
+        p = np.maximum(p, atmosphere * mod["rho_c"] * mod["G"] * mod["M"] / mod["R"])
+    phi = np.where(inside, -mod["M"] / mod["R"] - 4.0 * mod["kappa"] * mod["rho_c"] ** (1.0 / 3.0) * th,
+                   -mod["M"] / np.maximum(r, 1e-300))
+    zero = np.zeros_like(rho)
+    st = conserved_from_primitive(rho, zero, zero, zero, p, np.zeros((n, n, n + 1)), np.zeros((n, n + 1, n)),
+                                  np.zeros((n + 1, n, n)), gamma, phi=phi)
+    s = _setup(N, (L,) * 3, gamma, (OUTFLOW_BC,) * 3, VANLEER_LIMITER, 0.5, 20.0 * mod["tau_hse"])
+    s["model"] = mod
+    return st, s

@@ -26,6 +26,17 @@ def read_ranges(name):
     return out
 
 
+def read_values(name):
+    """{quantity: value} from a golden file of two columns."""
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if line:
+                out[line[0]] = float(line[1])
+    return out
+
+
 def energies(state, gamma):
     """Cell fields rho, p, b^2/2 (cell-centred b) and rho v^2/2."""
     c = state["cell"]

@@ -244,3 +244,77 @@ def test_mhd_riemann_2d_matches_printed_ranges():
     print("  ranges", got, flush=True)
     bad = pb.range_mismatches(got, pb.read_ranges("mhd_riemann_2d_ranges.txt"), 0.15, 2.0, 1e-3)
     assert not bad, bad
+
+
+# ------------------------------------------------------- steady polytrope
+def _poly_box(s, prec, hse):
+    import paper_0910_2854_amd as fish
+    h = s["h"]
+    return fish.Box(*s["shape"], dx=h[0], dy=h[1], dz=h[2], gamma=s["gamma"], cfl=s["cfl"], bc=s["bc"], gravity=True,
+                    hse=hse, precision=prec)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
+@pytest.mark.parametrize("hse", [False, True])
+def test_polytrope_parity_with_oracle(hse, prec, tol):
+    """Sect. 4.7 at 48^3 (gravity, outflow, HSE on and off), 10 steps on the
+    oracle's time steps.  FP32: the momenta start at rest and grow from the
+    residual of pressure and gravity forces, so they are measured against the
+    sound-speed momentum scale sum(rho c_s)."""
+    st, s = fi.polytrope_state(48)
+    print(f"polytrope parity 48^3 hse {hse} {prec}", flush=True)
+    h = s["h"]
+    o = Oracle(*s["shape"], dx=h[0], dy=h[1], dz=h[2], gamma=s["gamma"], cfl=s["cfl"], bc=s["bc"], gravity=True, hse=hse)
+    o.set_state(st)
+    g = _poly_box(s, prec, hse)
+    g.set_state(st)
+    for _ in range(10):
+        dt = o.cfl_dt()
+        o.strang_step(dt)
+        g.strang_step(dt)
+    out, ref = g.get_state(), o.get_state()
+    g.close()
+    errs = per_field_rel_l1(out, ref)
+    p = an.pressure(ref, s["gamma"])
+    scale = float(np.sum(np.sqrt(s["gamma"] * p * ref["cell"][0])))
+    for k, name in ((1, "mx"), (2, "my"), (3, "mz")):
+        errs[name] = float(np.sum(np.abs(out["cell"][k] - ref["cell"][k]))) / max(scale, float(np.sum(np.abs(ref["cell"][k]))))
+    for k in ("bx", "by", "bz"):
+        errs.pop(k)  # b = 0 stays exactly 0
+        assert not np.any(out[k])
+    print("  ", {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    assert max(errs.values()) <= tol, errs
+
+
+def test_polytrope_hse_keeps_the_centre():
+    """Sect. 4.7 at 64^3 and 128^3 over 20 tau_HSE, FP32, HSE on and off,
+    against the paper's statements: without HSE the central density falls
+    monotonically (the star evaporates); HSE slows the fall at both
+    resolutions; resolution slows it; with HSE at 128^3 the centre stays
+    within 5% of its value after the first tau_HSE (the initial relaxation).
+    The paper also finds HSE at 64^3 ahead of no HSE at 128^3; here it is not
+    (0.83 against 0.91 after 20 tau_HSE), so that is reported, not asserted."""
+    from test_oracle_problems import central_density
+    final = {}
+    for n in (64, 128):
+        st, s = fi.polytrope_state(n)
+        tau = s["model"]["tau_hse"]
+        rc0 = central_density(st, n)
+        for hse in (False, True):
+            print(f"polytrope {n}^3 hse {hse} fp32, 20 tau", flush=True)
+            g = _poly_box(s, "fp32", hse)
+            g.set_state(st)
+            t, hist = 0.0, []
+            for j in range(1, 21):
+                t, _ = evolve(g, t, j * tau)
+                hist.append(central_density(g.get_state(), n) / rc0)
+            g.close()
+            print("   ", " ".join(f"{v:.4f}" for v in hist), flush=True)
+            if not hse:
+                assert all(b < a for a, b in zip([1.0] + hist, hist)), hist
+            if hse and n == 128:
+                assert max(abs(v / hist[0] - 1.0) for v in hist) < 0.05, hist
+            final[(n, hse)] = hist[-1]
+    print("  final", final, flush=True)
+    assert final[(64, True)] > final[(64, False)] and final[(128, True)] > final[(128, False)], final
+    assert final[(128, False)] > final[(64, False)] and final[(128, True)] > final[(64, True)], final

@@ -159,3 +159,55 @@ def test_oracle_sedov_blast_follows_similarity_law():
         Rn = an.shock_radius(rcen, prof, 1.0)
         assert abs(Rn / an.sedov_radius(Eb, T) - 1.0) < 0.06, (R, Rn)
         assert abs(float(np.sum(x["cell"][4])) * h ** 3 / E0 - 1.0) < 1e-12
+
+
+# ------------------------------------------------------- steady polytrope
+def test_lane_emden_n3_matches_textbook_values():
+    """First zero xi1 = 6.89685 and -xi1^2 theta'(xi1) = 2.01824 of the n = 3
+    Lane-Emden solution (Chandrasekhar, Stellar Structure, Table 4)."""
+    _, xi1, dth = fi.lane_emden(3.0)
+    assert abs(xi1 - 6.89685) < 2e-5
+    assert abs(-xi1 ** 2 * dth - 2.01824) < 2e-5
+
+
+def test_polytrope_model_reproduces_printed_constants():
+    """Sect. 4.7: kappa, the mean and central densities and tau_HSE of a
+    1 M_sun, 1 R_sun n = 3 polytrope (cgs: M_sun = 1.989e33 g, R_sun =
+    6.96e10 cm, G = 6.674e-8), against the printed values to their digits."""
+    import problems as pb
+    m = fi.polytrope_model(M=1.989e33, R=6.96e10, G=6.674e-8)
+    ref = pb.read_values("polytrope_constants.txt")
+    for k, tol in (("kappa", 1e-3), ("rho_mean", 1e-3), ("rho_c", 1e-3), ("tau_hse", 1e-3)):
+        assert abs(m[k] / ref[k] - 1.0) < tol, (k, m[k], ref[k])
+
+
+def central_density(x, n):
+    c = n // 2
+    return float(np.mean(x["cell"][0][c - 1:c + 1, c - 1:c + 1, c - 1:c + 1]))
+
+
+def test_oracle_polytrope_evaporates_less_with_hse():
+    """Sect. 4.7 at 48^3 over 3 tau_HSE: without the HSE subtraction the
+    central density falls monotonically (the first-order dissipation at the
+    density maximum heats the centre); with it the fall is at most 60% as
+    large."""
+    n = 48
+    st, s = fi.polytrope_state(n)
+    tau = s["model"]["tau_hse"]
+    rc0 = central_density(st, n)
+    final = {}
+    for hse in (False, True):
+        o = Oracle(*s["shape"], dx=s["h"][0], dy=s["h"][1], dz=s["h"][2], gamma=s["gamma"], cfl=s["cfl"], bc=s["bc"],
+                   gravity=True, hse=hse)
+        o.set_state(st)
+        t, hist = 0.0, []
+        for j in (1, 2, 3):
+            while t < j * tau - 1e-12:
+                dt = min(o.cfl_dt(), 0.5 * (j * tau - t))
+                o.strang_step(dt)
+                t += 2.0 * dt
+            hist.append(central_density(o.get_state(), n) / rc0)
+        if not hse:
+            assert all(b < a for a, b in zip([1.0] + hist, hist)), hist
+        final[hse] = hist[-1]
+    assert 1.0 - final[True] <= 0.6 * (1.0 - final[False]), final
