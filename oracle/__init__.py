@@ -88,6 +88,13 @@ def _load():
     return lib
 
 
+def gravity_mode(gravity):
+    """False/0: none; True/1/"unsplit": Eqs. (41)-(43); 2/"split": Eqs. (38)-(40)."""
+    if isinstance(gravity, str):
+        return {"none": 0, "unsplit": 1, "split": 2}[gravity]
+    return int(gravity) if not isinstance(gravity, bool) else int(gravity)
+
+
 class OracleError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"oracle error {code}: {msg}")
@@ -118,7 +125,7 @@ class Oracle:
         p.predictor_alpha = float(predictor_alpha)
         for a in range(3):
             p.bc[a] = int(bc[a])
-        p.gravity, p.hse = int(bool(gravity)), int(bool(hse))
+        p.gravity, p.hse = gravity_mode(gravity), int(bool(hse))
         p.nthreads = int(nthreads)
         self.params = p
         h = ctypes.c_void_p()

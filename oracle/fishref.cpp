@@ -255,7 +255,7 @@ void gravity_source(const double* u, int d, double dphi2, double h, double* S) {
 void fluid_pencil(const Pencil& P, int n, int d, double dt, double h, const fishref_params& prm,
                   std::vector<double>* unew) {
   const int M = P.M;
-  const bool grav = prm.gravity != 0;
+  const bool grav = prm.gravity == 1;  // unsplit source inside the sweep
   const bool hse = prm.hse != 0;
   const double alpha = prm.predictor_alpha;
   auto lim = [&](double a, double b) { return prm.limiter == 0 ? minmod(a, b) : vanleer(a, b); };
@@ -334,7 +334,45 @@ void fluid_pencil(const Pencil& P, int n, int d, double dt, double h, const fish
   }
 }
 
+// Split gravity G_d(dt), Eqs. (39)-(40): on every real cell the momentum along
+// d changes by -dt rho (phi_i+1 - phi_i-1)/(2 h); density and internal energy
+// are left as they are, so the total energy changes by the change of the
+// kinetic energy (Sect. 2.3: the code's variables are density, momentum and
+// internal energy, and the total energy handed to L_d is their sum).
+void gravity_kick(Ctx* c, int d, double dt) {
+  const double h = c->h[d];
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int k = 0; k < c->n[2]; ++k)
+    for (int j = 0; j < c->n[1]; ++j)
+      for (int i = 0; i < c->n[0]; ++i) {
+        int lo[3] = {i, j, k}, hi[3] = {i, j, k};
+        lo[d] -= 1;
+        hi[d] += 1;
+        const size_t s = c->at(i, j, k);
+        const double dphi = c->phi[c->at(hi[0], hi[1], hi[2])] - c->phi[c->at(lo[0], lo[1], lo[2])];
+        const double rho = c->u[RHO][s];
+        const double m_old = c->u[MX + d][s];
+        const double m_new = m_old - dt * rho * dphi / (2.0 * h);
+        c->u[MX + d][s] = m_new;
+        c->u[EN][s] += 0.5 * m_new * m_new / rho - 0.5 * m_old * m_old / rho;
+      }
+}
+
+void apply_fluid_pencils(Ctx* c, int d, double dt);
+
+// L_d, Eq. (35) or, with unsplit gravity, Eqs. (41)-(43); with split gravity
+// G_d(dt/2) L_d(dt) G_d(dt/2), Eq. (38), L_d then without the source.
 void apply_fluid(Ctx* c, int d, double dt) {
+  if (c->p.gravity == 2) {
+    gravity_kick(c, d, 0.5 * dt);
+    apply_fluid_pencils(c, d, dt);
+    gravity_kick(c, d, 0.5 * dt);
+  } else {
+    apply_fluid_pencils(c, d, dt);
+  }
+}
+
+void apply_fluid_pencils(Ctx* c, int d, double dt) {
   fill_ghosts(c);
   const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
   const int n = c->n[d];
@@ -585,6 +623,7 @@ int fishref_create(const fishref_params* p, fishref_ctx** out) {
   if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || p->cfl > 1.0) return FISHREF_ERR_ARG;
   if (p->limiter != 0 && p->limiter != 1) return FISHREF_ERR_ARG;
   if (!(p->predictor_alpha >= 0.0) || p->predictor_alpha > 1.0) return FISHREF_ERR_ARG;
+  if (p->gravity < 0 || p->gravity > 2) return FISHREF_ERR_ARG;
   if (p->hse && !p->gravity) return FISHREF_ERR_ARG;
   fishref_ctx* c = new (std::nothrow) fishref_ctx();
   if (!c) return FISHREF_ERR_NOMEM;

@@ -43,7 +43,8 @@ typedef struct fishref_params {
   int32_t limiter;        /* 0 minmod Eq. (29), 1 van Leer Eq. (30)              */
   double predictor_alpha; /* predictor freezing-speed scale in [0, 1] (Sect. 2.2)*/
   int32_t bc[3];          /* per axis: 0 periodic, 1 outflow (zeroth order)      */
-  int32_t gravity;        /* 0 none, 1 fixed potential, unsplit Eqs. (41)-(43)   */
+  int32_t gravity;        /* 0 none; fixed potential: 1 unsplit Eqs. (41)-(43),  */
+                          /* 2 split G(dt/2) L G(dt/2), Eqs. (38)-(40)          */
   int32_t hse;            /* 0/1 hydrostatic-gradient subtraction Eqs. (51)-(57) */
   int32_t nthreads;       /* OpenMP threads, 0 = runtime default                 */
 } fishref_params;
