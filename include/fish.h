@@ -7,8 +7,8 @@
  * One context advances one Cartesian box of cells.  The cell state is
  * u = (rho, m_x, m_y, m_z, E) (cell averages, Eq. 8) and the magnetic field
  * lives on the faces (face averages, Eqs. 9-11).  A double step applies the
- * symmetric product of fluid sweeps L_d (Sect. 2.2, with the unsplit gravity
- * of Sect. 2.3 and the hydrostatic-gradient subtraction of Eqs. 51-57) and
+ * symmetric product of fluid sweeps L_d (Sect. 2.2, with the unsplit or split
+ * gravity of Sect. 2.3 and the hydrostatic-gradient subtraction of Eqs. 51-57) and
  * constrained-transport field sweeps B_d (Sect. 2.4), Eqs. (12)-(13).
  *
  * Conventions shared by every call:
@@ -68,7 +68,11 @@ typedef struct fish_params {
   int32_t bc[3];             /* per axis FISH_PERIODIC or FISH_OUTFLOW (Sect. 4, 4.6)   */
   int32_t precision;         /* FISH_FP64, or FISH_FP32 storage and arithmetic with FP64
                                 pressure recovery, CFL reduction and totals            */
-  int32_t gravity;           /* 0 none, 1 fixed potential, unsplit Eqs. (41)-(43)       */
+  int32_t gravity;           /* 0 none; with a fixed potential phi: 1 unsplit, the
+                                source in the predictor and corrector, Eqs. (41)-(43);
+                                2 split, each L_d replaced by G_d(dt/2) L_d G_d(dt/2),
+                                Eqs. (38)-(40): G_d changes m_d by -rho dphi/dx dt and
+                                holds rho and the internal energy                      */
   int32_t hse;               /* 0/1 hydrostatic-gradient subtraction (needs gravity)    */
   int32_t device;            /* HIP device ordinal                                      */
   void* stream;              /* hipStream_t to enqueue on, NULL = default stream        */
@@ -205,7 +209,7 @@ typedef struct fish_batch_params {
   int32_t limiter;
   double predictor_alpha;
   int32_t precision;
-  int32_t gravity;
+  int32_t gravity;           /* as in fish_params */
   int32_t hse;
   int32_t device;
   void* stream;              /* NULL: the batch creates its own (graphs cannot

@@ -102,6 +102,16 @@ EXPORTS = ("fish_create", "fish_destroy", "fish_last_error", "fish_set_state", "
 KERNEL_FLUID, KERNEL_FIELD, KERNEL_CHECK = 1, 2, 8
 KINDS = ("fluid_x", "fluid_y", "fluid_z", "field_x", "field_y", "field_z", "check")
 
+GRAVITY_MODES = {"none": 0, "unsplit": 1, "split": 2}
+
+
+def gravity_mode(gravity):
+    """False/"none": 0; True/"unsplit": 1 (Eqs. 41-43); "split": 2 (Eqs. 38-40)."""
+    if isinstance(gravity, str):
+        return GRAVITY_MODES[gravity]
+    return int(gravity)
+
+
 _lib = None
 
 
@@ -239,7 +249,7 @@ class Box:
         for a in range(3):
             p.bc[a] = int(bc[a])
         p.precision = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
-        p.gravity, p.hse = int(bool(gravity)), int(bool(hse))
+        p.gravity, p.hse = gravity_mode(gravity), int(bool(hse))
         p.device = int(device)
         self._allocator = None
         if stream is None or use_torch_allocator:
@@ -380,7 +390,7 @@ def box_pool_bytes(n, precision="fp32", gravity=False, bc=(PERIODIC,) * 3):
     """Device bytes one box (nx, ny, nz) takes in a batch."""
     lib = load_library()
     prec = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
-    return int(lib.fish_box_pool_bytes(ctypes.byref(_geom(n, bc=bc)), prec, int(bool(gravity))))
+    return int(lib.fish_box_pool_bytes(ctypes.byref(_geom(n, bc=bc)), prec, gravity_mode(gravity)))
 
 
 def _batch_params(owner, pool_bytes, max_boxes, gamma, limiter, predictor_alpha, precision, gravity, hse, device,
@@ -390,7 +400,7 @@ def _batch_params(owner, pool_bytes, max_boxes, gamma, limiter, predictor_alpha,
     p.limiter = int(limiter)
     p.predictor_alpha = float(predictor_alpha)
     p.precision = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
-    p.gravity, p.hse = int(bool(gravity)), int(bool(hse))
+    p.gravity, p.hse = gravity_mode(gravity), int(bool(hse))
     p.device = int(device)
     p.pool_bytes = int(pool_bytes)
     p.max_boxes = int(max_boxes)

@@ -184,7 +184,7 @@ class Engine {
   int fluid_dispatch();
   template <typename T, int D, int LIM>
   void fluid_dispatch_lim();
-  template <typename T, int D, bool GRAV, bool HSE, int LIM>
+  template <typename T, int D, int GRAV, bool HSE, int LIM>
   void launch_fluid();
   template <typename T, int D>
   int field_sweep();

@@ -732,7 +732,7 @@ static WorkList make_wl(const Engine* e, int kind) {
 }
 
 // ------------------------------------------------------------ sub-operators
-template <typename T, int D, bool GRAV, bool HSE, int LIM>
+template <typename T, int D, int GRAV, bool HSE, int LIM>
 void Engine::launch_fluid() {
   FluidLaunch<T> L;
   for (int k = 0; k < 5; ++k) {
@@ -762,11 +762,11 @@ void Engine::launch_fluid() {
 template <typename T, int D, int LIM>
 void Engine::fluid_dispatch_lim() {
   if (!cfg.gravity)
-    launch_fluid<T, D, false, false, LIM>();
-  else if (!cfg.hse)
-    launch_fluid<T, D, true, false, LIM>();
+    launch_fluid<T, D, 0, false, LIM>();
+  else if (cfg.gravity == 1)
+    cfg.hse ? launch_fluid<T, D, 1, true, LIM>() : launch_fluid<T, D, 1, false, LIM>();
   else
-    launch_fluid<T, D, true, true, LIM>();
+    cfg.hse ? launch_fluid<T, D, 2, true, LIM>() : launch_fluid<T, D, 2, false, LIM>();
 }
 
 template <typename T, int D>

@@ -31,7 +31,7 @@ int check_common(double gamma, int limiter, double alpha, int precision, int gra
   if (limiter != FISH_MINMOD && limiter != FISH_VANLEER) return FISH_ERR_ARG;
   if (!(alpha >= 0.0) || alpha > 1.0) return FISH_ERR_ARG;
   if (precision != FISH_FP64 && precision != FISH_FP32) return FISH_ERR_ARG;
-  if ((gravity != 0 && gravity != 1) || (hse != 0 && hse != 1)) return FISH_ERR_ARG;
+  if (gravity < 0 || gravity > 2 || (hse != 0 && hse != 1)) return FISH_ERR_ARG;
   if (hse && !gravity) return FISH_ERR_ARG;
   return FISH_OK;
 }

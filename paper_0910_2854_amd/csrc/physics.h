@@ -156,6 +156,17 @@ __device__ __forceinline__ void gravity_source(T rho, T mD, T dphi2, T inv2h, T*
   S[EN] = -mD * gr;
 }
 
+// Split gravity G_D over half a step, Eqs. (39)-(40): m_D -= rho gh with
+// gh = (dt/2)(phi_i+1 - phi_i-1)/(2 h).  Density and internal energy stay, so
+// E changes by the kinetic energy, (m'^2 - m^2)/(2 rho) = -gh (m + m')/2.
+template <typename T, int D>
+__device__ __forceinline__ void gravity_kick(T* u, T gh) {
+  const T m = u[MX + D];
+  const T mn = m - u[RHO] * gh;
+  u[MX + D] = mn;
+  u[EN] = u[EN] - gh * (T(0.5) * (m + mn));
+}
+
 // ----------------------------------------------------------- index maps
 // Periodic axes wrap; outflow axes copy the nearest real entry (zeroth-order
 // extrapolation).  A face array along its own normal has n+1 real faces on

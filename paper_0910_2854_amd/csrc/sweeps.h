@@ -298,22 +298,32 @@ struct FluidHist {
 // One stream position: loads of cell c in (uc, bc, phc); returns the
 // corrected state of cell c-3 in un.  u3 is the state of cell c-3 when the
 // caller reloads it (lanes policy); otherwise the history chain supplies it.
-template <typename T, int D, bool GRAV, bool HSE, int LIM, typename H, bool RELOAD_U3>
-__device__ __forceinline__ void fluid_position(const T* uc, const Vec<T, 3>& bcc, T phc, const T* u3_loaded,
-                                               const FluidConsts<T>& k, const FluidHist<T, HSE>& hi,
-                                               FluidHist<T, HSE>& ho, T* un) {
-  // cell quantities of u at c and c-1
-  CellQ<T, HSE> q0;
-  cell_quantities<T, D, HSE>(uc, bcc.v, k.gamma, q0);
-  const CellQ<T, HSE> q0m = H::prev(q0, hi.q0, ho.q0);
-  const Vec<T, 3> bcm = prev_vec<H>(bcc, hi.bc, ho.bc);
+// GRAV: 0 none, 1 unsplit source in the predictor and corrector (Eqs. 41-43),
+// 2 split kicks G(dt/2) L G(dt/2) (Eqs. 38-40): the entering cell is kicked
+// by gh_c = (dt/2)(phi_c+1 - phi_c-1)/(2h), which the caller computes from
+// its own loads (the first positions of a stream have no history of phi),
+// before its first use; the output cell c-3 after its corrector, by the same
+// factor formed from the history of phi.
+template <typename T, int D, int GRAV, bool HSE, int LIM, typename H, bool RELOAD_U3>
+__device__ __forceinline__ void fluid_position(const T* uc_in, const Vec<T, 3>& bcc, T phc, T gh_c,
+                                               const T* u3_loaded, const FluidConsts<T>& k,
+                                               const FluidHist<T, HSE>& hi, FluidHist<T, HSE>& ho, T* un) {
   T phm1 = T(0), phm2 = T(0), phm3 = T(0), phm4 = T(0);
-  if (GRAV || HSE) {
+  if (GRAV != 0 || HSE) {
     phm1 = H::prev(phc, hi.ph1, ho.ph1);
     phm2 = H::prev(phm1, hi.ph2, ho.ph2);
     phm3 = H::prev(phm2, hi.ph3, ho.ph3);
     phm4 = H::prev(phm3, hi.ph4, ho.ph4);
   }
+  T uc[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) uc[i] = uc_in[i];
+  if (GRAV == 2) gravity_kick<T, D>(uc, gh_c);
+  // cell quantities of u at c and c-1
+  CellQ<T, HSE> q0;
+  cell_quantities<T, D, HSE>(uc, bcc.v, k.gamma, q0);
+  const CellQ<T, HSE> q0m = H::prev(q0, hi.q0, ho.q0);
+  const Vec<T, 3> bcm = prev_vec<H>(bcc, hi.bc, ho.bc);
   // predictor flux at interface c-1/2 (Eq. 24, dissipation scaled by alpha)
   T Q[5];
   Vec<T, 5> F1;
@@ -323,7 +333,7 @@ __device__ __forceinline__ void fluid_position(const T* uc, const Vec<T, 3>& bcc
   const Vec<T, 5> F1m = prev_vec<H>(F1, hi.F1, ho.F1);
   // predictor half step of cell c-1 (Eq. 41)
   T up[5];
-  if (GRAV) {
+  if (GRAV == 1) {
     T S[5];
     gravity_source<T, D>(q0m.u[RHO], q0m.u[MX + D], phc - phm2, k.inv2h, S);
 #pragma unroll
@@ -360,9 +370,12 @@ __device__ __forceinline__ void fluid_position(const T* uc, const Vec<T, 3>& bcc
   const Vec<T, 5> F2m = prev_vec<H>(F2, hi.F2, ho.F2);
   // state of cell c-3 before the sweep
   T u3[5];
+  // kick of c-3 (split gravity): phi of c-2 and c-4
+  const T gh3 = GRAV == 2 ? k.half_dt * (phm2 - phm4) * k.inv2h : T(0);
   if (RELOAD_U3) {
 #pragma unroll
     for (int i = 0; i < 5; ++i) u3[i] = u3_loaded[i];
+    if (GRAV == 2) gravity_kick<T, D>(u3, gh3);  // bitwise the kick it had on entry
   } else {
     Vec<T, 5> um1;
 #pragma unroll
@@ -373,7 +386,7 @@ __device__ __forceinline__ void fluid_position(const T* uc, const Vec<T, 3>& bcc
     for (int i = 0; i < 5; ++i) u3[i] = um3.v[i];
   }
   // corrector of cell c-3 (Eq. 43)
-  if (GRAV) {
+  if (GRAV == 1) {
     const T rpm2 = H::prev(up[RHO], hi.rp1, ho.rp1);   // rho' of c-2
     const T rpm3 = H::prev(rpm2, hi.rp2, ho.rp2);      // rho' of c-3
     const T mpm2 = H::prev(up[MX + D], hi.mp1, ho.mp1);
@@ -385,6 +398,7 @@ __device__ __forceinline__ void fluid_position(const T* uc, const Vec<T, 3>& bcc
   } else {
 #pragma unroll
     for (int i = 0; i < 5; ++i) un[i] = u3[i] - k.k_full * (F2.v[i] - F2m.v[i]);
+    if (GRAV == 2) gravity_kick<T, D>(un, gh3);
   }
   (void)phm3;
 }
@@ -440,7 +454,7 @@ __device__ __forceinline__ bool strided_map(int wave, int nA, int nO, int nseg, 
 }
 
 // Strided policy (D = y or z): one lane per pencil segment, lanes along x.
-template <typename T, int D, bool GRAV, bool HSE, int LIM>
+template <typename T, int D, int GRAV, bool HSE, int LIM>
 __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidLaunch<T> L) {
   static_assert(D != 0, "x sweeps use the lanes policy");
   constexpr int A = 0;  // lanes walk along x
@@ -477,7 +491,7 @@ __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidLaunch<T> L) {
   struct In {
     T u[5];
     Vec<T, 3> bc;
-    T phi;
+    T phi, gh;
   };
   // inputs of position it (loads only: issued one position ahead of use)
   auto load = [&](int it) {
@@ -494,12 +508,15 @@ __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidLaunch<T> L) {
     in.bc.v[T1] = T(0.5) * (ld(b1, base) + ld(b1, hi1));
     in.bc.v[T2] = T(0.5) * (ld(b2, base) + ld(b2, hi2));
     in.phi = GRAV ? load_phi(a.phi, lbase, stD, s, nD, bcD) : T(0);
+    in.gh = GRAV == 2 ? k.half_dt * (load_phi(a.phi, lbase, stD, s + 1, nD, bcD) -
+                                     load_phi(a.phi, lbase, stD, s - 1, nD, bcD)) * k.inv2h
+                      : T(0);
     return in;
   };
   auto compute = [&](int it, const In& in, const FluidHist<T, HSE>& hi, FluidHist<T, HSE>& ho) {
     const int s = s0 - 3 + it;
     T un[5];
-    fluid_position<T, D, GRAV, HSE, LIM, StridedHist, false>(in.u, in.bc, in.phi, nullptr, k, hi, ho, un);
+    fluid_position<T, D, GRAV, HSE, LIM, StridedHist, false>(in.u, in.bc, in.phi, in.gh, nullptr, k, hi, ho, un);
     if (it >= 6 && s - 3 < s1 && active) {
       const long long o = (long long)(s - 3) * stD;
 #pragma unroll
@@ -575,7 +592,7 @@ __device__ __forceinline__ void publish_cfl(double cmax, int bad, Scalars* sc) {
 // Lanes policy (D = x): each wave streams rows_per_wave whole x rows.  With
 // CFL the sweep also reduces the CFL speed of the state it writes (the last
 // sub-operator of a double step leaves the next step's time step ready).
-template <typename T, bool GRAV, bool HSE, int LIM, bool CFL>
+template <typename T, int GRAV, bool HSE, int LIM, bool CFL>
 __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
   constexpr int D = 0;
   const BoxDesc* d;
@@ -606,7 +623,7 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
   struct In {
     T u[5], u3[5];
     Vec<T, 3> bc;
-    T phi;
+    T phi, gh;
     T b3[3];      // cell-centred field of the output cell (CFL only)
     unsigned o3;  // byte offset of the output cell c-3
     int co;       // output cell index along x
@@ -636,6 +653,9 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
     in.bc.v[1] = T(0.5) * (ld(a.b[1], ms) + ld(a.b[1], ms + dy));
     in.bc.v[2] = T(0.5) * (ld(a.b[2], ms) + ld(a.b[2], ms + dz));
     in.phi = GRAV ? load_phi(a.phi, (long long)base, 1, cpos, nx, g.bc[0]) : T(0);
+    in.gh = GRAV == 2 ? k.half_dt * (load_phi(a.phi, (long long)base, 1, cpos + 1, nx, g.bc[0]) -
+                                     load_phi(a.phi, (long long)base, 1, cpos - 1, nx, g.bc[0])) * k.inv2h
+                      : T(0);
     in.o3 = (base + (unsigned)map_cell_near(cpos - 3, nx, g.bc[0])) * z4;
 #pragma unroll
     for (int i = 0; i < 5; ++i) in.u3[i] = ld(a.u[i], in.o3);
@@ -651,7 +671,7 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
   };
   auto compute = [&](const In& in, const FluidHist<T, HSE>& hi, FluidHist<T, HSE>& ho) {
     T un[5];
-    fluid_position<T, D, GRAV, HSE, LIM, LaneHist, true>(in.u, in.bc, in.phi, in.u3, k, hi, ho, un);
+    fluid_position<T, D, GRAV, HSE, LIM, LaneHist, true>(in.u, in.bc, in.phi, in.gh, in.u3, k, hi, ho, un);
     const bool out = in.valid && in.co >= 0 && in.co < nx;
     if (out) {
 #pragma unroll

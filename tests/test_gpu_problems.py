@@ -247,26 +247,28 @@ def test_mhd_riemann_2d_matches_printed_ranges():
 
 
 # ------------------------------------------------------- steady polytrope
-def _poly_box(s, prec, hse):
+def _poly_box(s, prec, hse, gravity="unsplit"):
     import paper_0910_2854_amd as fish
     h = s["h"]
-    return fish.Box(*s["shape"], dx=h[0], dy=h[1], dz=h[2], gamma=s["gamma"], cfl=s["cfl"], bc=s["bc"], gravity=True,
-                    hse=hse, precision=prec)
+    return fish.Box(*s["shape"], dx=h[0], dy=h[1], dz=h[2], gamma=s["gamma"], cfl=s["cfl"], bc=s["bc"],
+                    gravity=gravity, hse=hse, precision=prec)
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
 @pytest.mark.parametrize("hse", [False, True])
-def test_polytrope_parity_with_oracle(hse, prec, tol):
-    """Sect. 4.7 at 48^3 (gravity, outflow, HSE on and off), 10 steps on the
-    oracle's time steps.  FP32: the momenta start at rest and grow from the
+@pytest.mark.parametrize("gravity", ["unsplit", "split"])
+def test_polytrope_parity_with_oracle(gravity, hse, prec, tol):
+    """Sect. 4.7 at 48^3 (unsplit or split gravity, outflow, HSE on and off),
+    10 steps on the oracle's time steps.  FP32: the momenta start at rest and grow from the
     residual of pressure and gravity forces, so they are measured against the
     sound-speed momentum scale sum(rho c_s)."""
     st, s = fi.polytrope_state(48)
-    print(f"polytrope parity 48^3 hse {hse} {prec}", flush=True)
+    print(f"polytrope parity 48^3 {gravity} hse {hse} {prec}", flush=True)
     h = s["h"]
-    o = Oracle(*s["shape"], dx=h[0], dy=h[1], dz=h[2], gamma=s["gamma"], cfl=s["cfl"], bc=s["bc"], gravity=True, hse=hse)
+    o = Oracle(*s["shape"], dx=h[0], dy=h[1], dz=h[2], gamma=s["gamma"], cfl=s["cfl"], bc=s["bc"], gravity=gravity,
+               hse=hse)
     o.set_state(st)
-    g = _poly_box(s, prec, hse)
+    g = _poly_box(s, prec, hse, gravity)
     g.set_state(st)
     for _ in range(10):
         dt = o.cfl_dt()
