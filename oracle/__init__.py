@@ -40,7 +40,7 @@ LIB_PATH = os.path.join(HERE, "libfishref.so")
 
 OK, ERR_ARG, ERR_NOMEM, ERR_STATE, ERR_UNSUPPORTED = 0, 1, 2, 4, 5
 PERIODIC, OUTFLOW = 0, 1
-MINMOD, VANLEER = 0, 1
+MINMOD, VANLEER, MACH_SWITCH = 0, 1, 2
 
 
 class _Params(ctypes.Structure):

@@ -154,6 +154,7 @@ struct CellQ {
   double p;      // gas pressure
   double d;      // freezing speed |v_d| + c_F, Eq. (21)
   double xi[5];  // hydrostatic gradient vector, Eq. (50)
+  bool supersonic;  // |v| > c_S (the limiter switch of Sect. 2.2)
 };
 
 CellQ cell_quantities(const double* u, const double* b, int d, double gamma) {
@@ -186,6 +187,7 @@ CellQ cell_quantities(const double* u, const double* b, int d, double gamma) {
   c.cF = cf;
   c.cS = std::sqrt(a2);
   c.p = p;
+  c.supersonic = v[0] * v[0] + v[1] * v[1] + v[2] * v[2] > a2;
   c.d = std::fabs(v[d]) + cf;
   c.xi[RHO] = -u[RHO];
   c.xi[MX] = -u[MX];
@@ -258,7 +260,15 @@ void fluid_pencil(const Pencil& P, int n, int d, double dt, double h, const fish
   const bool grav = prm.gravity == 1;  // unsplit source inside the sweep
   const bool hse = prm.hse != 0;
   const double alpha = prm.predictor_alpha;
-  auto lim = [&](double a, double b) { return prm.limiter == 0 ? minmod(a, b) : vanleer(a, b); };
+  // Limiter of cell c: minmod (Eq. 29), van Leer (Eq. 30), or, for the switch
+  // used in core-collapse runs (Sect. 2.2), van Leer where the flow is
+  // subsonic and minmod where it is supersonic.  reading: a cell is
+  // supersonic when its speed |v| exceeds its sound speed c_S on the state the
+  // limited differences are taken from (the half-step state).
+  auto lim = [&](const CellQ& c, double a, double b) {
+    const bool mm = prm.limiter == 0 || (prm.limiter == 2 && c.supersonic);
+    return mm ? minmod(a, b) : vanleer(a, b);
+  };
 
   // cell quantities of u^n, positions G-3 .. G+n+2
   std::vector<CellQ> C0(M);
@@ -324,7 +334,7 @@ void fluid_pencil(const Pencil& P, int n, int d, double dt, double h, const fish
   for (int m = G - 1; m < G + n; ++m)
     for (int k = 0; k < 5; ++k)
       F2[k][m] = 0.5 * (C1[m].F[k] + C1[m + 1].F[k]) - 0.5 * Qc[k][m] +
-                 0.5 * (lim(ap[k][m - 1], ap[k][m]) - lim(am[k][m], am[k][m + 1]));
+                 0.5 * (lim(C1[m], ap[k][m - 1], ap[k][m]) - lim(C1[m + 1], am[k][m], am[k][m + 1]));
   // Corrector full step, Eq. (43) (Eq. 35 without gravity), real cells.
   for (int m = G; m < G + n; ++m) {
     double S[5] = {0, 0, 0, 0, 0};
@@ -506,7 +516,8 @@ void apply_field(Ctx* c, int d, double dt) {
             w[m] = 0.5 * (vd[c->at(r[0], r[1], r[2])] + vd[c->at(q[0], q[1], q[2])]);
             b[m] = bt[c->at(q[0], q[1], q[2])];
           }
-          field_row(w, b, nd, dt, c->h[d], c->p.limiter, bnew, e);
+          // the limiter switch is a fluid choice; the field advection keeps van Leer
+          field_row(w, b, nd, dt, c->h[d], c->p.limiter == 0 ? 0 : 1, bnew, e);
           std::copy(e.begin(), e.end(), emf[s].begin() + ((size_t)co * (nt + 1) + ft) * (nd + 1));
           if (ft < real_faces_t)
             for (int i = 0; i < nd; ++i) {
@@ -621,7 +632,7 @@ int fishref_create(const fishref_params* p, fishref_ctx** out) {
     if (p->bc[a] != PERIODIC && p->bc[a] != OUTFLOW) return FISHREF_ERR_ARG;
   }
   if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || p->cfl > 1.0) return FISHREF_ERR_ARG;
-  if (p->limiter != 0 && p->limiter != 1) return FISHREF_ERR_ARG;
+  if (p->limiter < 0 || p->limiter > 2) return FISHREF_ERR_ARG;
   if (!(p->predictor_alpha >= 0.0) || p->predictor_alpha > 1.0) return FISHREF_ERR_ARG;
   if (p->gravity < 0 || p->gravity > 2) return FISHREF_ERR_ARG;
   if (p->hse && !p->gravity) return FISHREF_ERR_ARG;

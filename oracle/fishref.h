@@ -40,7 +40,8 @@ typedef struct fishref_params {
   double dx, dy, dz;      /* uniform spacing > 0 (Sect. 2.1)                     */
   double gamma;           /* ratio of specific heats > 1, Eq. (5)                */
   double cfl;             /* Courant number k of Eq. (14), 0 < k <= 1            */
-  int32_t limiter;        /* 0 minmod Eq. (29), 1 van Leer Eq. (30)              */
+  int32_t limiter;        /* 0 minmod Eq. (29), 1 van Leer Eq. (30), 2 van Leer   */
+                          /* where |v| <= c_S, minmod where |v| > c_S (fluid)   */
   double predictor_alpha; /* predictor freezing-speed scale in [0, 1] (Sect. 2.2)*/
   int32_t bc[3];          /* per axis: 0 periodic, 1 outflow (zeroth order)      */
   int32_t gravity;        /* 0 none; fixed potential: 1 unsplit Eqs. (41)-(43),  */
