@@ -55,7 +55,7 @@ typedef enum fish_status {
 } fish_status;
 
 enum { FISH_PERIODIC = 0, FISH_OUTFLOW = 1 };
-enum { FISH_MINMOD = 0, FISH_VANLEER = 1 };
+enum { FISH_MINMOD = 0, FISH_VANLEER = 1, FISH_MACH_SWITCH = 2 };
 enum { FISH_FP64 = 0, FISH_FP32 = 1 };
 
 typedef struct fish_params {
@@ -63,7 +63,11 @@ typedef struct fish_params {
   double dx, dy, dz;         /* uniform spacing > 0 (Sect. 2.1)                         */
   double gamma;              /* ratio of specific heats > 1, Eq. (5)                    */
   double cfl;                /* Courant number k of Eq. (14), 0 < k <= 1                */
-  int32_t limiter;           /* FISH_MINMOD Eq. (29) or FISH_VANLEER Eq. (30)           */
+  int32_t limiter;           /* FISH_MINMOD Eq. (29), FISH_VANLEER Eq. (30), or
+                                FISH_MACH_SWITCH: van Leer where a cell's half-step
+                                state has |v| <= c_S, minmod where |v| > c_S, in the
+                                fluid sweeps (Sect. 2.2); the field advection then
+                                keeps van Leer                                        */
   double predictor_alpha;    /* predictor dissipation scale in [0, 1] (Sect. 2.2)       */
   int32_t bc[3];             /* per axis FISH_PERIODIC or FISH_OUTFLOW (Sect. 4, 4.6)   */
   int32_t precision;         /* FISH_FP64, or FISH_FP32 storage and arithmetic with FP64

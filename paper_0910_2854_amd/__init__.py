@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libfish.so")
 
 FISH_OK, FISH_ERR_ARG, FISH_ERR_NOMEM, FISH_ERR_DEVICE, FISH_ERR_STATE, FISH_ERR_UNSUPPORTED = range(6)
 PERIODIC, OUTFLOW = 0, 1
-MINMOD, VANLEER = 0, 1
+MINMOD, VANLEER, MACH_SWITCH = 0, 1, 2
 FP64, FP32 = 0, 1
 
 _ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)

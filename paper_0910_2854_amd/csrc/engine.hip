@@ -773,8 +773,10 @@ template <typename T, int D>
 int Engine::fluid_dispatch() {
   if (cfg.limiter == 0)
     fluid_dispatch_lim<T, D, 0>();
-  else
+  else if (cfg.limiter == 1)
     fluid_dispatch_lim<T, D, 1>();
+  else
+    fluid_dispatch_lim<T, D, 2>();
   for (int k = 0; k < 5; ++k) cur[k] = 1 - cur[k];
   return launch_check();
 }
@@ -812,6 +814,7 @@ int Engine::field_sweep_lim() {
 
 template <typename T, int D>
 int Engine::field_sweep() {
+  // the limiter switch (limiter 2) is a fluid choice: the field advection keeps van Leer
   return cfg.limiter == 0 ? field_sweep_lim<T, D, 0>() : field_sweep_lim<T, D, 1>();
 }
 

@@ -28,7 +28,7 @@ namespace {
 
 int check_common(double gamma, int limiter, double alpha, int precision, int gravity, int hse) {
   if (!(gamma > 1.0) || !std::isfinite(gamma)) return FISH_ERR_ARG;
-  if (limiter != FISH_MINMOD && limiter != FISH_VANLEER) return FISH_ERR_ARG;
+  if (limiter != FISH_MINMOD && limiter != FISH_VANLEER && limiter != FISH_MACH_SWITCH) return FISH_ERR_ARG;
   if (!(alpha >= 0.0) || alpha > 1.0) return FISH_ERR_ARG;
   if (precision != FISH_FP64 && precision != FISH_FP32) return FISH_ERR_ARG;
   if (gravity < 0 || gravity > 2 || (hse != 0 && hse != 1)) return FISH_ERR_ARG;

@@ -47,6 +47,7 @@ struct CellQ {
   T F[5];
   T vd, cF, d;
   T cS, xiE;
+  T sup;  // 1 where |v| > c_S (the limiter switch of Sect. 2.2), else 0
 };
 
 // E = rho e + m^2/(2 rho) + b^2/2 and p = (gamma-1) rho e (Sect. 2.1, Eq. 5):
@@ -90,6 +91,7 @@ __device__ __forceinline__ void cell_quantities(const T* u, const T* b, double g
   c.vd = v[D];
   c.cF = cf;
   c.d = fabs(v[D]) + cf;
+  c.sup = v[0] * v[0] + v[1] * v[1] + v[2] * v[2] > a2 ? T(1) : T(0);
   if (HSE) {
     c.cS = fsqrt(a2);
     c.xiE = -(u[EN] + p);
@@ -114,6 +116,13 @@ __device__ __forceinline__ T vanleer(T a, T b) {
 template <typename T, int LIM>
 __device__ __forceinline__ T limit(T a, T b) {
   return LIM == 0 ? minmod(a, b) : vanleer(a, b);
+}
+// Limiter of one cell: LIM 0 minmod, 1 van Leer, 2 the switch of Sect. 2.2
+// (minmod where the cell is supersonic, sup = 1; van Leer elsewhere).
+template <typename T, int LIM>
+__device__ __forceinline__ T limit_cell(T sup, T a, T b) {
+  if (LIM == 2) return sup != T(0) ? minmod(a, b) : vanleer(a, b);
+  return limit<T, LIM>(a, b);
 }
 
 // Dissipation Q_j at the interface between cells L and R, so that the

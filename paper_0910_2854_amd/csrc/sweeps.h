@@ -281,17 +281,17 @@ struct FluidHist {
   CellQ<T, HSE> q0, q1;
   Vec<T, 3> bc;
   Vec<T, 5> F1, ap, am, Lp, bs, F2, ua, ub;
-  T ph1, ph2, ph3, ph4, rp1, rp2, mp1, mp2;
+  T ph1, ph2, ph3, ph4, rp1, rp2, mp1, mp2, sp1;
   __device__ void zero() {
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       q0.u[k] = q0.F[k] = q1.u[k] = q1.F[k] = T(0);
       F1.v[k] = ap.v[k] = am.v[k] = Lp.v[k] = bs.v[k] = F2.v[k] = ua.v[k] = ub.v[k] = T(0);
     }
-    q0.vd = q0.cF = q0.d = q0.cS = q0.xiE = T(0);
-    q1.vd = q1.cF = q1.d = q1.cS = q1.xiE = T(0);
+    q0.vd = q0.cF = q0.d = q0.cS = q0.xiE = q0.sup = T(0);
+    q1.vd = q1.cF = q1.d = q1.cS = q1.xiE = q1.sup = T(0);
     bc.v[0] = bc.v[1] = bc.v[2] = T(0);
-    ph1 = ph2 = ph3 = ph4 = rp1 = rp2 = mp1 = mp2 = T(0);
+    ph1 = ph2 = ph3 = ph4 = rp1 = rp2 = mp1 = mp2 = sp1 = T(0);
   }
 };
 
@@ -360,13 +360,16 @@ __device__ __forceinline__ void fluid_position(const T* uc_in, const Vec<T, 3>& 
   const Vec<T, 5> apm = prev_vec<H>(ap, hi.ap, ho.ap);
   const Vec<T, 5> amm = prev_vec<H>(am, hi.am, ho.am);
   const Vec<T, 5> bsm = prev_vec<H>(bs, hi.bs, ho.bs);
-  // limited second-order flux at interface c-5/2 (Eq. 34)
+  // limited second-order flux at interface c-5/2 (Eq. 34); both limiters
+  // taken here belong to cell c-2 (its half-step state decides the switch)
+  const T sup2 = LIM == 2 ? H::prev(q1.sup, hi.sp1, ho.sp1) : T(0);
   Vec<T, 5> Lp, F2;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) Lp.v[i] = limit<T, LIM>(apm.v[i], ap.v[i]);
+  for (int i = 0; i < 5; ++i) Lp.v[i] = limit_cell<T, LIM>(sup2, apm.v[i], ap.v[i]);
   const Vec<T, 5> Lpm = prev_vec<H>(Lp, hi.Lp, ho.Lp);
 #pragma unroll
-  for (int i = 0; i < 5; ++i) F2.v[i] = bsm.v[i] + T(0.5) * (Lpm.v[i] - limit<T, LIM>(amm.v[i], am.v[i]));
+  for (int i = 0; i < 5; ++i)
+    F2.v[i] = bsm.v[i] + T(0.5) * (Lpm.v[i] - limit_cell<T, LIM>(sup2, amm.v[i], am.v[i]));
   const Vec<T, 5> F2m = prev_vec<H>(F2, hi.F2, ho.F2);
   // state of cell c-3 before the sweep
   T u3[5];
