@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+LIMITERS = {"minmod": 0, "vanleer": 1, "switch": 2}
 METRIC = "cell-updates/s per Strang step (FP32 vs FP64) + % HBM roofline; p50/p99 latency"
 
 
@@ -60,12 +61,12 @@ def load_traffic(name, esize, cells):
     return rec.get("bytes_per_launch")
 
 
-def run_gpu(fish, torch, st, n, precision, steps, warmup, cfl, segment, autotune=True):
+def run_gpu(fish, torch, st, n, precision, steps, warmup, cfl, segment, autotune=True, limiter=1):
     """Time `steps` Strang steps (dt from the device CFL step) in segments of at
     most `segment` steps, each started from the initial state: the state is
     re-uploaded and synchronised before a segment's clock starts and checked
     after it stops, so every timed step advances a physically valid state."""
-    box = fish.Box(*n, precision=precision, cfl=cfl)
+    box = fish.Box(*n, precision=precision, cfl=cfl, limiter=limiter)
     box.set_state(st)
     tuned = box.autotune(reps=5) if autotune else None
     for _ in range(warmup):
@@ -348,7 +349,7 @@ def bench_sphere(args, torch, fish, fi):
     t0 = time.perf_counter()
     st = fi.sphere_state(n, seed=0)
     log(f"  {time.perf_counter() - t0:.1f} s")
-    box = fish.Box(*n, precision="fp32", bc=(fish.OUTFLOW,) * 3, gravity=True, hse=True, cfl=0.5)
+    box = fish.Box(*n, precision="fp32", bc=(fish.OUTFLOW,) * 3, gravity=args.gravity, hse=True, cfl=0.5)
     box.set_state(st)
     del st
     for _ in range(args.warmup):
@@ -381,7 +382,7 @@ def bench_sphere(args, torch, fish, fi):
         "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{n[0]}^3 stratified sphere rho = 1/(1+(r/0.1)^2) with 1% noise, matching potential "
-                               "and hydrostatic pressure, beta 100, outflow boundaries, unsplit gravity + HSE, "
+                               f"and hydrostatic pressure, beta 100, outflow boundaries, {args.gravity} gravity + HSE, "
                                "gamma 5/3, CFL 0.5, FP32 with FP64 pressure recovery", "cells": ncell},
         "latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99)},
         "step_roofline": {"bytes_per_cell": 408, "achieved_GBs": value * 408 / 1e9, "peak_GBs": HBM_PEAK_GBS,
@@ -500,6 +501,10 @@ def main():
     ap.add_argument("--workload", choices=("box", "batch", "serve", "sphere", "problems"), default="box",
                     help="box: the 256^3 box (default); batch: 2048 boxes of uneven size; serve: request loop; "
                          "sphere: 512^3 sphere with gravity + HSE; problems: the validation problems of Sect. 4.2-4.6")
+    ap.add_argument("--limiter", choices=tuple(LIMITERS), default="vanleer",
+                    help="box workload: van Leer (default), minmod, or the Mach switch of Sect. 2.2")
+    ap.add_argument("--gravity", choices=("unsplit", "split"), default="unsplit",
+                    help="sphere workload: unsplit source (default) or split kicks, Sect. 2.3")
     ap.add_argument("--boxes", type=int, default=2048)
     ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
     ap.add_argument("--single-sample", type=int, default=8, help="boxes per size for the single-box comparison")
@@ -551,7 +556,7 @@ def main():
     for prec in ("fp32",) + (() if args.no_fp64 else ("fp64",)):
         log(f"GPU {prec}: {args.warmup} warmup + {args.steps} timed steps")
         res[prec] = run_gpu(fish, torch, st, n, prec, args.steps, args.warmup, cfl, args.segment,
-                            autotune=not args.no_autotune)
+                            autotune=not args.no_autotune, limiter=LIMITERS[args.limiter])
         r = res[prec]
         log(f"  {r['wall'] * 1e3 / args.steps:.3f} ms/step, fluid launch avg "
             f"{r['fluid_ms'] / max(1, r['fluid_launches']):.3f} ms, state_ok={r['state_ok']}")
@@ -583,7 +588,8 @@ def main():
                         "(this box loses positivity after 6 steps, the FP64 oracle included; there are no floors)",
             "precision": "FP32 storage and arithmetic, FP64 pressure recovery / CFL reduction",
             "cells": ncell,
-            "limiter": "van Leer",
+            "limiter": {"vanleer": "van Leer", "minmod": "minmod",
+                        "switch": "van Leer where subsonic, minmod where supersonic"}[args.limiter],
             "autotuned": r["tuned"],
         },
         "latency_ms": {"p50": pct(r["step_ms"], 50), "p99": pct(r["step_ms"], 99)},
@@ -606,7 +612,7 @@ def main():
                        "state_ok": r64["state_ok"]}
     if not args.no_cpu:
         log(f"CPU oracle baseline: {args.cpu_steps} step(s)")
-        out["cpu_baseline"] = cpu_baseline(st, n, cfl, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(st, n, cfl, args.cpu_steps, limiter=LIMITERS[args.limiter])
         log(f"  {out['cpu_baseline']['value']:.3e} cell-updates/s")
     print(json.dumps(out), flush=True)
 
