@@ -20,13 +20,19 @@ flux to round-off; discrete div b unchanged; axis equivariance; second-order
 convergence on linear Alfven, fast and entropy waves and on the circularly
 polarised Alfven wave of Sect. 4.1; the exact Riemann solution of a Sod tube;
 Rankine-Hugoniot jumps of a hydrodynamic and a perpendicular MHD shock; TVD of
-the field advection; the closed forms of the fast speed; the HSE reductions.
+the field advection; the closed forms of the fast speed; the HSE reductions;
+split gravity (closed-form kick, hydrostatic atmosphere at second order); the
+Mach limiter switch (reduces to either limiter per regime); irregular meshes
+(conservation, per-cell divergence, second order on stretched meshes, exact
+face interpolation of a linear shear, reduction to the uniform mesh).
 
 Parity unpinned (readings the paper does not fix and no pin can separate):
 the exact directional fast speed in the freezing speed, the interface-local
 freezing speed inside the limited flux differences, the predictor dissipation
 scale (default 1), the default limiter (van Leer), the details of the
-second-order field-advection corrector, and the form of the HSE corrector.
+second-order field-advection corrector, the form of the HSE corrector, the
+slope form of the second-order fluxes on irregular meshes (differences over
+centre distances, carried half a cell) and the width of ghost cells.
 """
 from __future__ import annotations
 
@@ -80,6 +86,7 @@ def _load():
     lib.fishref_cfl_dt.argtypes = [vp, P(d)]
     lib.fishref_strang_step.argtypes = [vp, d]
     lib.fishref_apply.argtypes = [vp, ctypes.c_int, ctypes.c_int, d]
+    lib.fishref_set_spacing.argtypes = [vp, ctypes.c_int, P(d)]
     lib.fishref_diagnostics.argtypes = [vp, P(d)]
     for name in ("fishref_create", "fishref_set_state", "fishref_get_state", "fishref_cfl_dt",
                  "fishref_strang_step", "fishref_apply", "fishref_diagnostics"):
@@ -188,6 +195,13 @@ class Oracle:
         """One sub-operator: op 'L' (fluid) or 'B' (field), direction 0/1/2."""
         code = {"L": 0, "B": 1}[op] if isinstance(op, str) else int(op)
         self._check(self._lib.fishref_apply(self._h, code, int(direction), float(dt)))
+
+    def set_spacing(self, axis, widths):
+        """Irregular mesh (Sect. 2.5): the widths of the cells along axis."""
+        w = np.ascontiguousarray(widths, dtype=np.float64)
+        if w.shape != (self.shape[2 - axis],):
+            raise ValueError("one width per cell along the axis")
+        self._check(self._lib.fishref_set_spacing(self._h, int(axis), _ptr(w)))
 
     def diagnostics(self):
         out = np.zeros(10)

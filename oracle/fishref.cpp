@@ -44,6 +44,11 @@ struct Ctx {
   std::vector<double> u[5];
   std::vector<double> b[3];  // face f along the normal stored at padded cell f
   std::vector<double> phi;
+  // Irregular Cartesian mesh (Sect. 2.5): the width of every padded cell
+  // along each axis (ghosts take the width of the cell they copy or wrap to).
+  // Uniform meshes keep the formulas of Sects. 2.2-2.4 exactly.
+  bool nonuniform = false;
+  std::vector<double> hs[3];
   bool have_state = false;
   double t = 0.0;
   int status = FISHREF_OK;
@@ -56,6 +61,19 @@ struct Ctx {
   // number of real faces of b[a] along its normal
   int nface(int a) const { return p.bc[a] == OUTFLOW ? n[a] + 1 : n[a]; }
 };
+
+// Widths of the padded cells along axis a from the real widths w[0..n-1]:
+// a periodic ghost takes the width of the cell it wraps to, an outflow ghost
+// that of the nearest real cell (the cell it copies).
+void fill_spacing(Ctx* c, int a, const double* w) {
+  const int n = c->n[a];
+  c->hs[a].assign(n + 2 * G, 0.0);
+  for (int m = 0; m < n + 2 * G; ++m) {
+    int i = m - G;
+    if (i < 0 || i >= n) i = (c->p.bc[a] == PERIODIC || n == 1) ? ((i % n) + n) % n : (i < 0 ? 0 : n - 1);
+    c->hs[a][m] = w[i];
+  }
+}
 
 int fail(Ctx* c, int code, const std::string& msg) {
   c->err = msg;
@@ -244,17 +262,23 @@ void dissipation(const CellQ& L, const CellQ& R, double phiL, double phiR, bool 
 }
 
 // Gravitational source of the unsplit scheme, Eq. (42), for cell i with the
-// centred potential difference phi_i+1 - phi_i-1.  reading: the source is
-// -(0, rho e_d, m_d) dphi/dx (the minus sign of Eq. 36, dropped in Eq. 42).
-void gravity_source(const double* u, int d, double dphi2, double h, double* S) {
-  const double g = dphi2 / (2.0 * h);
+// centred potential difference phi_i+1 - phi_i-1 over the distance span of
+// the two cell centres (2 dx; on an irregular mesh dx_i-1/2 + dx_i +
+// dx_i+1/2).  reading: the source is -(0, rho e_d, m_d) dphi/dx (the minus
+// sign of Eq. 36, dropped in Eq. 42).
+void gravity_source(const double* u, int d, double dphi2, double span, double* S) {
+  const double g = dphi2 / span;
   for (int k = 0; k < 5; ++k) S[k] = 0.0;
   S[MX + d] = -u[RHO] * g;
   S[EN] = -u[MX + d] * g;
 }
 
 // L_d on one pencil; writes unew for the real cells G..G+n-1.
-void fluid_pencil(const Pencil& P, int n, int d, double dt, double h, const fishref_params& prm,
+// centre distance of padded cells m-1 and m+1 along the pencil
+double span_of(const double* hs, int m, double h) { return hs ? 0.5 * hs[m - 1] + hs[m] + 0.5 * hs[m + 1] : 2.0 * h; }
+
+// hs: widths of the padded cells along d on an irregular mesh, else null.
+void fluid_pencil(const Pencil& P, int n, int d, double dt, double h, const double* hs, const fishref_params& prm,
                   std::vector<double>* unew) {
   const int M = P.M;
   const bool grav = prm.gravity == 1;  // unsplit source inside the sweep
@@ -293,9 +317,10 @@ void fluid_pencil(const Pencil& P, int n, int d, double dt, double h, const fish
   for (auto& v : up) v.assign(M, 0.0);
   for (int m = G - 2; m < G + n + 2; ++m) {
     double S[5] = {0, 0, 0, 0, 0};
-    if (grav) gravity_source(C0[m].u, d, P.phi[m + 1] - P.phi[m - 1], h, S);
+    if (grav) gravity_source(C0[m].u, d, P.phi[m + 1] - P.phi[m - 1], span_of(hs, m, h), S);
+    const double hm = hs ? hs[m] : h;  // Eq. (37) on an irregular mesh
     for (int k = 0; k < 5; ++k)
-      up[k][m] = P.u[k][m] - dt / (2.0 * h) * (F1[k][m] - F1[k][m - 1]) + 0.5 * dt * S[k];
+      up[k][m] = P.u[k][m] - dt / (2.0 * hm) * (F1[k][m] - F1[k][m - 1]) + 0.5 * dt * S[k];
   }
   // Cell quantities of the half-step state u^n' (field unchanged).
   std::vector<CellQ> C1(M);
@@ -329,18 +354,32 @@ void fluid_pencil(const Pencil& P, int n, int d, double dt, double h, const fish
   // F = F+_i + F-_i+1 + (phi(dF+_i-1/2, dF+_i+1/2) - phi(dF-_i+1/2, dF-_i+3/2))/2.
   // The limiters are homogeneous of degree one, so the 1/dx of Eq. (27) and
   // the dx/2 of Eq. (34) cancel.
+  // On an irregular mesh (Sect. 2.5) the slopes of the piecewise-linear F+-
+  // divide each difference by the distance of its two cell centres and are
+  // carried half a cell width to the interface: a correction
+  // (dx_i/2) phi(dF_i-1/2 / delta_i-1/2, dF_i+1/2 / delta_i+1/2), which is
+  // phi(dF_i-1/2, dF_i+1/2)/2 on a uniform mesh.
   std::vector<double> F2[5];
   for (auto& v : F2) v.assign(M, 0.0);
   for (int m = G - 1; m < G + n; ++m)
-    for (int k = 0; k < 5; ++k)
-      F2[k][m] = 0.5 * (C1[m].F[k] + C1[m + 1].F[k]) - 0.5 * Qc[k][m] +
-                 0.5 * (lim(C1[m], ap[k][m - 1], ap[k][m]) - lim(C1[m + 1], am[k][m], am[k][m + 1]));
+    for (int k = 0; k < 5; ++k) {
+      F2[k][m] = 0.5 * (C1[m].F[k] + C1[m + 1].F[k]) - 0.5 * Qc[k][m];
+      if (!hs) {
+        F2[k][m] += 0.5 * (lim(C1[m], ap[k][m - 1], ap[k][m]) - lim(C1[m + 1], am[k][m], am[k][m + 1]));
+      } else {
+        const double dl = 0.5 * (hs[m - 1] + hs[m]), dr = 0.5 * (hs[m] + hs[m + 1]);
+        const double dr2 = 0.5 * (hs[m + 1] + hs[m + 2]);
+        F2[k][m] += 0.5 * hs[m] * lim(C1[m], ap[k][m - 1] / dl, ap[k][m] / dr) -
+                    0.5 * hs[m + 1] * lim(C1[m + 1], am[k][m] / dr, am[k][m + 1] / dr2);
+      }
+    }
   // Corrector full step, Eq. (43) (Eq. 35 without gravity), real cells.
   for (int m = G; m < G + n; ++m) {
     double S[5] = {0, 0, 0, 0, 0};
-    if (grav) gravity_source(C1[m].u, d, P.phi[m + 1] - P.phi[m - 1], h, S);
+    if (grav) gravity_source(C1[m].u, d, P.phi[m + 1] - P.phi[m - 1], span_of(hs, m, h), S);
+    const double hm = hs ? hs[m] : h;
     for (int k = 0; k < 5; ++k)
-      unew[k][m - G] = P.u[k][m] - dt / h * (F2[k][m] - F2[k][m - 1]) + dt * S[k];
+      unew[k][m - G] = P.u[k][m] - dt / hm * (F2[k][m] - F2[k][m - 1]) + dt * S[k];
   }
 }
 
@@ -349,6 +388,8 @@ void fluid_pencil(const Pencil& P, int n, int d, double dt, double h, const fish
 // are left as they are, so the total energy changes by the change of the
 // kinetic energy (Sect. 2.3: the code's variables are density, momentum and
 // internal energy, and the total energy handed to L_d is their sum).
+int q_of(int i, int j, int k, int d) { return d == 0 ? i : (d == 1 ? j : k); }
+
 void gravity_kick(Ctx* c, int d, double dt) {
   const double h = c->h[d];
 #pragma omp parallel for collapse(2) schedule(static)
@@ -362,7 +403,10 @@ void gravity_kick(Ctx* c, int d, double dt) {
         const double dphi = c->phi[c->at(hi[0], hi[1], hi[2])] - c->phi[c->at(lo[0], lo[1], lo[2])];
         const double rho = c->u[RHO][s];
         const double m_old = c->u[MX + d][s];
-        const double m_new = m_old - dt * rho * dphi / (2.0 * h);
+        const double span = c->nonuniform ? 0.5 * c->hs[d][lo[d] + G] + c->hs[d][q_of(i, j, k, d) + G] +
+                                                0.5 * c->hs[d][hi[d] + G]
+                                          : 2.0 * h;
+        const double m_new = m_old - dt * rho * dphi / span;
         c->u[MX + d][s] = m_new;
         c->u[EN][s] += 0.5 * m_new * m_new / rho - 0.5 * m_old * m_old / rho;
       }
@@ -420,7 +464,7 @@ void apply_fluid_pencils(Ctx* c, int d, double dt) {
           }
           P.phi[m] = have_phi ? c->phi[s] : 0.0;
         }
-        fluid_pencil(P, n, d, dt, c->h[d], c->p, unew);
+        fluid_pencil(P, n, d, dt, c->h[d], c->nonuniform ? c->hs[d].data() : nullptr, c->p, unew);
         for (int i = 0; i < n; ++i) {
           int q[3];
           q[d] = i;
@@ -439,8 +483,9 @@ void apply_fluid_pencils(Ctx* c, int d, double dt) {
 // b[m]: the b_t face values along the row.  Outputs bnew for the real cells
 // and the second-order edge flux (EMF) at d-faces f = 0..n (face f between
 // cells f-1 and f).
+// hs: widths of the padded cells along d on an irregular mesh, else null.
 void field_row(const std::vector<double>& w, const std::vector<double>& b, int n, double dt, double h,
-               int limiter, std::vector<double>& bnew, std::vector<double>& emf) {
+               const double* hs, int limiter, std::vector<double>& bnew, std::vector<double>& emf) {
   const int M = n + 2 * G;
   auto lim = [&](double a, double c) { return limiter == 0 ? minmod(a, c) : vanleer(a, c); };
   // 1-2-1 smoothing of the face velocity along d, Eq. (66).  reading: the two
@@ -460,22 +505,33 @@ void field_row(const std::vector<double>& w, const std::vector<double>& b, int n
   // Half-step predictor (Sect. 2.4: first-order predictor, as for the fluid).
   std::vector<double> bp(M, 0.0), fp(M, 0.0);
   for (int m = G - 2; m < G + n + 2; ++m) {
-    bp[m] = b[m] - dt / (2.0 * h) * (phi1[m] - phi1[m - 1]);
+    bp[m] = b[m] - dt / (2.0 * (hs ? hs[m] : h)) * (phi1[m] - phi1[m - 1]);
     fp[m] = vb[m] * bp[m];
   }
   // Second-order corrector flux: piecewise-linear upwind reconstruction of the
   // half-step flux v b' with the TVD limiter (Sect. 2.4, last paragraph).
   // reading: the limited slope of v b' on the upwind cell, evaluated at the
-  // interface.  Interfaces m+1/2 for m = G-1 .. G+n-1.
+  // interface.  Interfaces m+1/2 for m = G-1 .. G+n-1.  On an irregular mesh
+  // the slope divides each difference by its centre distance and is carried
+  // half the upwind cell's width (as for the fluid corrector).
   std::vector<double> phi2(M, 0.0);
   for (int m = G - 1; m < G + n; ++m) {
-    if (V[m] > 0.0)
-      phi2[m] = fp[m] + 0.5 * lim(fp[m] - fp[m - 1], fp[m + 1] - fp[m]);
-    else
-      phi2[m] = fp[m + 1] - 0.5 * lim(fp[m + 1] - fp[m], fp[m + 2] - fp[m + 1]);
+    if (!hs) {
+      if (V[m] > 0.0)
+        phi2[m] = fp[m] + 0.5 * lim(fp[m] - fp[m - 1], fp[m + 1] - fp[m]);
+      else
+        phi2[m] = fp[m + 1] - 0.5 * lim(fp[m + 1] - fp[m], fp[m + 2] - fp[m + 1]);
+    } else {
+      auto delta = [&](int a) { return 0.5 * (hs[a] + hs[a + 1]); };  // centres a, a+1
+      if (V[m] > 0.0)
+        phi2[m] = fp[m] + 0.5 * hs[m] * lim((fp[m] - fp[m - 1]) / delta(m - 1), (fp[m + 1] - fp[m]) / delta(m));
+      else
+        phi2[m] = fp[m + 1] - 0.5 * hs[m + 1] *
+                                  lim((fp[m + 1] - fp[m]) / delta(m), (fp[m + 2] - fp[m + 1]) / delta(m + 1));
+    }
   }
   // Advection update of b_t, Eq. (63) with the flux difference along d.
-  for (int m = G; m < G + n; ++m) bnew[m - G] = b[m] - dt / h * (phi2[m] - phi2[m - 1]);
+  for (int m = G; m < G + n; ++m) bnew[m - G] = b[m] - dt / (hs ? hs[m] : h) * (phi2[m] - phi2[m - 1]);
   // Edge flux at d-face f lies at interface (G + f - 1) + 1/2.
   for (int f = 0; f <= n; ++f) emf[f] = phi2[G + f - 1];
 }
@@ -512,12 +568,21 @@ void apply_field(Ctx* c, int d, double dt) {
             q[o] = co;
             int r[3] = {q[0], q[1], q[2]};
             r[t] = ft - 1;
-            // Eq. (65): v_d at the t-face, mean of the two cells sharing it.
-            w[m] = 0.5 * (vd[c->at(r[0], r[1], r[2])] + vd[c->at(q[0], q[1], q[2])]);
+            // Eq. (65): v_d at the t-face, mean of the two cells sharing it;
+            // on an irregular mesh the linear interpolation between their
+            // centres (Sect. 2.5), in a form odd under mirroring.
+            const double vlo = vd[c->at(r[0], r[1], r[2])], vhi = vd[c->at(q[0], q[1], q[2])];
+            if (!c->nonuniform) {
+              w[m] = 0.5 * (vlo + vhi);
+            } else {
+              const double hlo = c->hs[t][ft - 1 + G], hhi = c->hs[t][ft + G];
+              w[m] = (vlo * hhi + vhi * hlo) / (hlo + hhi);
+            }
             b[m] = bt[c->at(q[0], q[1], q[2])];
           }
           // the limiter switch is a fluid choice; the field advection keeps van Leer
-          field_row(w, b, nd, dt, c->h[d], c->p.limiter == 0 ? 0 : 1, bnew, e);
+          field_row(w, b, nd, dt, c->h[d], c->nonuniform ? c->hs[d].data() : nullptr, c->p.limiter == 0 ? 0 : 1,
+                    bnew, e);
           std::copy(e.begin(), e.end(), emf[s].begin() + ((size_t)co * (nt + 1) + ft) * (nd + 1));
           if (ft < real_faces_t)
             for (int i = 0; i < nd; ++i) {
@@ -553,7 +618,10 @@ void apply_field(Ctx* c, int d, double dt) {
         q[t1] = c1;
         q[t2] = c2;
         const size_t s = c->at(q[0], q[1], q[2]);
-        bd[s] = bd[s] + dt * ((e1hi - e1lo) / c->h[t1] + (e2hi - e2lo) / c->h[t2]);
+        // on an irregular mesh the widths of the face's cell across t1 and t2
+        const double w1 = c->nonuniform ? c->hs[t1][c1 + G] : c->h[t1];
+        const double w2 = c->nonuniform ? c->hs[t2][c2 + G] : c->h[t2];
+        bd[s] = bd[s] + dt * ((e1hi - e1lo) / w1 + (e2hi - e2lo) / w2);
       }
 }
 
@@ -578,7 +646,10 @@ int cfl(Ctx* c, double* dt_out) {
           if (c->n[d] == 1) continue;
           CellQ q = cell_quantities(u, b, d, c->p.gamma);
           if (!(q.p > 0.0) || !(u[RHO] > 0.0) || !std::isfinite(q.d)) bad = true;
-          cmax = std::max(cmax, (std::fabs(q.vd) + q.cF) / c->h[d]);
+          // Eq. (42) on an irregular mesh: the width of this cell along d
+          const int idx[3] = {i, j, k};
+          const double hd = c->nonuniform ? c->hs[d][idx[d] + G] : c->h[d];
+          cmax = std::max(cmax, (std::fabs(q.vd) + q.cF) / hd);
         }
       }
   if (bad) return FISHREF_ERR_STATE;
@@ -643,6 +714,10 @@ int fishref_create(const fishref_params* p, fishref_ctx** out) {
     c->n[a] = n[a];
     c->h[a] = h[a];
     c->N[a] = n[a] + 2 * G;
+  }
+  for (int a = 0; a < 3; ++a) {
+    const std::vector<double> w(n[a], h[a]);
+    fill_spacing(c, a, w.data());
   }
   try {
     for (auto& v : c->u) v.assign(c->ncell_padded(), 0.0);
@@ -779,6 +854,15 @@ int fishref_strang_step(fishref_ctx* c, double dt) {
   return FISHREF_OK;
 }
 
+int fishref_set_spacing(fishref_ctx* c, int axis, const double* widths) {
+  if (!c || !widths || axis < 0 || axis > 2) return FISHREF_ERR_ARG;
+  for (int i = 0; i < c->n[axis]; ++i)
+    if (!(widths[i] > 0.0) || !std::isfinite(widths[i])) return fail(c, FISHREF_ERR_ARG, "bad cell width");
+  fill_spacing(c, axis, widths);
+  c->nonuniform = true;
+  return FISHREF_OK;
+}
+
 int fishref_diagnostics(fishref_ctx* c, double* out) {
   if (!c || !out) return FISHREF_ERR_ARG;
   if (!c->have_state) return fail(c, FISHREF_ERR_ARG, "no state");
@@ -792,11 +876,15 @@ int fishref_diagnostics(fishref_ctx* c, double* out) {
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
         const size_t s = c->at(i, j, k);
-        for (int f = 0; f < 5; ++f) tot[f] += c->u[f][s];
+        const double hx = c->nonuniform ? c->hs[0][i + G] : c->h[0];
+        const double hy = c->nonuniform ? c->hs[1][j + G] : c->h[1];
+        const double hz = c->nonuniform ? c->hs[2][k + G] : c->h[2];
+        const double cw = c->nonuniform ? hx * hy * hz / vol : 1.0;  // cell volume / vol
+        for (int f = 0; f < 5; ++f) tot[f] += c->nonuniform ? c->u[f][s] * cw : c->u[f][s];
         // Eq. (62)
-        const double div = (c->b[0][c->at(i + 1, j, k)] - c->b[0][s]) / c->h[0] +
-                           (c->b[1][c->at(i, j + 1, k)] - c->b[1][s]) / c->h[1] +
-                           (c->b[2][c->at(i, j, k + 1)] - c->b[2][s]) / c->h[2];
+        const double div = (c->b[0][c->at(i + 1, j, k)] - c->b[0][s]) / hx +
+                           (c->b[1][c->at(i, j + 1, k)] - c->b[1][s]) / hy +
+                           (c->b[2][c->at(i, j, k + 1)] - c->b[2][s]) / hz;
         divmax = std::max(divmax, std::fabs(div));
       }
   for (int f = 0; f < 5; ++f) out[f] = tot[f] * vol;
@@ -808,7 +896,15 @@ int fishref_diagnostics(fishref_ctx* c, double* out) {
       for (int j = 0; j < lim[1]; ++j)
         for (int i = 0; i < lim[0]; ++i) {
           const double v = c->b[a][c->at(i, j, k)];
-          sum += v;
+          if (c->nonuniform) {  // face area over the uniform one
+            const int q[3] = {i, j, k};
+            double area = 1.0;
+            for (int e = 0; e < 3; ++e)
+              if (e != a) area *= c->hs[e][q[e] + G] / c->h[e];
+            sum += v * area;
+          } else {
+            sum += v;
+          }
           bmax = std::max(bmax, std::fabs(v));
         }
     out[5 + a] = sum * vol / c->h[a];

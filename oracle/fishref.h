@@ -72,6 +72,11 @@ int fishref_strang_step(fishref_ctx* c, double dt);
  * (Sect. 2.4); dir 0/1/2 = x/y/z. */
 int fishref_apply(fishref_ctx* c, int op, int dir, double dt);
 
+/* Irregular Cartesian mesh (Sect. 2.5): the widths of the n cells along axis
+ * (0/1/2), all > 0.  From then on every sweep, the CFL step and the
+ * diagnostics use per-cell widths (the other axes keep theirs). */
+int fishref_set_spacing(fishref_ctx* c, int axis, const double* widths);
+
 /* out[0..4]  = sums of rho, m_x, m_y, m_z, E times the cell volume,
  * out[5..7]  = sums of bx, by, bz over the real faces times the face area,
  * out[8]     = max |div b| over cells, Eq. (62),
