@@ -134,8 +134,24 @@ int fish_sweep(fish_ctx* ctx, int op, int dir, double dt);
 /* Diagnostics of the current state, Eq. (18) and Eq. (62), reduced in FP64 in
  * a fixed order: out[0..4] = sums of rho, m_x, m_y, m_z, E times the cell
  * volume; out[5..7] = sums of bx, by, bz over the real faces times the face
- * area; out[8] = max |div b|; out[9] = max |b| over faces.  Synchronises. */
+ * area; out[8] = max |div b|; out[9] = max |b| over faces.  Synchronises.
+ * FISH_ERR_UNSUPPORTED on an irregular mesh (fish_set_spacing). */
 int fish_diagnostics(fish_ctx* ctx, double* out10);
+
+/* Irregular Cartesian mesh (Sect. 2.5): the widths of the n cells along axis
+ * (0/1/2), host FP64 array of n values, all finite and > 0, copied.  From
+ * then on every sweep and the CFL step use per-cell widths: the flux
+ * differences of a cell divide by its own width (Eq. 37), the second-order
+ * slopes divide each difference by the distance of its two cell centres and
+ * are carried half a cell width to the interface, the gravity gradient spans
+ * the two neighbouring centres, the face velocity of Eq. (65) interpolates
+ * linearly between the two cell centres, the constraint update (Eq. 64) uses
+ * the widths of the face's cell, and the CFL step takes each cell's widths
+ * (Eq. 42).  Ghost cells take the width of the cell they map to.  Axes not
+ * set keep the uniform width of fish_params.  Synchronises the stream.
+ * FISH_ERR_ARG for a bad axis, a null array or a width that is not finite
+ * and positive. */
+int fish_set_spacing(fish_ctx* ctx, int axis, const double* widths);
 
 /* Bytes of device memory the context holds (state, double buffers, scratch). */
 size_t fish_device_bytes(const fish_ctx* ctx);

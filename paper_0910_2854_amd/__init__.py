@@ -98,7 +98,7 @@ EXPORTS = ("fish_create", "fish_destroy", "fish_last_error", "fish_set_state", "
            "fish_batch_remove", "fish_batch_get", "fish_batch_box_info", "fish_batch_step",
            "fish_batch_use_graph", "fish_batch_autotune", "fish_batch_sync", "fish_batch_timing_enable",
            "fish_batch_timing_read", "fish_set_shape", "fish_batch_set_shape", "fish_server_create", "fish_server_destroy", "fish_server_last_error",
-           "fish_server_batch", "fish_server_submit", "fish_server_pump", "fish_server_stats")
+           "fish_server_batch", "fish_server_submit", "fish_server_pump", "fish_server_stats", "fish_set_spacing")
 KERNEL_FLUID, KERNEL_FIELD, KERNEL_CHECK = 1, 2, 8
 KINDS = ("fluid_x", "fluid_y", "fluid_z", "field_x", "field_y", "field_z", "check")
 
@@ -166,6 +166,8 @@ def load_library(path: str = LIB_PATH):
     lib.fish_batch_timing_enable.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.fish_batch_timing_read.argtypes = [vp, P(ctypes.c_int), P(d)]
     lib.fish_set_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int32]
+    lib.fish_set_spacing.argtypes = [vp, ctypes.c_int, P(ctypes.c_double)]
+    lib.fish_set_spacing.restype = ctypes.c_int
     lib.fish_batch_set_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int32]
     lib.fish_set_shape.restype = ctypes.c_int
     lib.fish_batch_set_shape.restype = ctypes.c_int
@@ -345,6 +347,13 @@ class Box:
         out = np.zeros(10)
         self._check(self._lib.fish_diagnostics(self._h, _dptr(out)))
         return _diag_dict(out)
+
+    def set_spacing(self, axis, widths):
+        """Irregular mesh (Sect. 2.5): the widths of the cells along axis."""
+        w = np.ascontiguousarray(widths, dtype=np.float64)
+        if w.shape != (self.shape[2 - axis],):
+            raise ValueError("one width per cell along the axis")
+        self._check(self._lib.fish_set_spacing(self._h, int(axis), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
     def set_shape(self, kind, target, xcd_remap=0, alt_layout=0):
         """Set one kind's work shape (kind: a name of KINDS)."""

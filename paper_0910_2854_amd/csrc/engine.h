@@ -77,6 +77,10 @@ class Engine {
   long long cap = 0;  // elements per pool
   DeviceBuf pool[2][8];
   DeviceBuf phi;
+  // irregular mesh (Sect. 2.5, one box at slot 0): the widths of its cells per
+  // axis in the storage precision; every sweep then takes per-cell widths
+  DeviceBuf wid[3];
+  bool nonuniform = false;
   int cur[8]{};
   std::map<long long, long long> free_list;  // offset -> length (elements)
 
@@ -166,6 +170,7 @@ class Engine {
   int autotune(int reps, int* chosen);
   int set_shape(int kind, int value);
   int set_graph(bool on);
+  int set_spacing(int axis, const double* widths);  // one box: irregular mesh along axis
 
  private:
   int ensure_stage(size_t bytes);
@@ -176,6 +181,8 @@ class Engine {
   int enqueue_step_cfl();                   // the launches of one CFL-stepped double step
   int last_sweep_and_cfl();
   void invalidate_graph();
+  template <typename T>
+  int set_spacing_t(int axis, const double* widths);
   void drop_retired_graphs();
   int build_lists();
   template <typename T>
@@ -184,12 +191,16 @@ class Engine {
   int fluid_dispatch();
   template <typename T, int D, int LIM>
   void fluid_dispatch_lim();
-  template <typename T, int D, int GRAV, bool HSE, int LIM>
+  template <typename T, int D, int GRAV, bool HSE, int LIM, bool NU>
   void launch_fluid();
+  template <typename T, int D, int GRAV, bool HSE, int LIM>
+  void launch_fluid_mesh();
   template <typename T, int D>
   int field_sweep();
   template <typename T, int D, int LIM>
   int field_sweep_lim();
+  template <typename T, int D, int LIM, bool NU>
+  void launch_field();
   template <typename T>
   int launch_check_cfl();
   template <typename T>

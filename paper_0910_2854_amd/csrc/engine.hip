@@ -167,6 +167,8 @@ void Engine::release() {
   for (int b = 0; b < 2; ++b)
     for (int f = 0; f < 8; ++f) dev_free(pool[b][f]);
   dev_free(phi);
+  for (int k = 0; k < 3; ++k) dev_free(wid[k]);
+  nonuniform = false;
   dev_free(scal);
   dev_free(table);
   for (int k = 0; k < K_NUM; ++k) dev_free(lists[k]);
@@ -733,6 +735,14 @@ static WorkList make_wl(const Engine* e, int kind) {
 
 // ------------------------------------------------------------ sub-operators
 template <typename T, int D, int GRAV, bool HSE, int LIM>
+void Engine::launch_fluid_mesh() {
+  if (nonuniform)
+    launch_fluid<T, D, GRAV, HSE, LIM, true>();
+  else
+    launch_fluid<T, D, GRAV, HSE, LIM, false>();
+}
+
+template <typename T, int D, int GRAV, bool HSE, int LIM, bool NU>
 void Engine::launch_fluid() {
   FluidLaunch<T> L;
   for (int k = 0; k < 5; ++k) {
@@ -741,6 +751,7 @@ void Engine::launch_fluid() {
   }
   for (int k = 0; k < 3; ++k) L.b[k] = (const T*)pool[cur[5 + k]][5 + k].ptr;
   L.phi = (const T*)phi.ptr;
+  for (int k = 0; k < 3; ++k) L.wid[k] = NU ? (const T*)wid[k].ptr : nullptr;
   L.gamma = cfg.gamma;
   L.alpha = cfg.alpha;
   L.wl = make_wl(this, K_FLUID_X + D);
@@ -750,23 +761,23 @@ void Engine::launch_fluid() {
   TimedLaunch tl(this, 1);
   if (D == 0) {
     if (last_fluid_cfl)
-      hipLaunchKernelGGL((fluid_lanes_kernel<T, GRAV, HSE, LIM, true>), grid, dim3(kBlock), 0, cfg.stream, L);
+      hipLaunchKernelGGL((fluid_lanes_kernel<T, GRAV, HSE, LIM, true, NU>), grid, dim3(kBlock), 0, cfg.stream, L);
     else
-      hipLaunchKernelGGL((fluid_lanes_kernel<T, GRAV, HSE, LIM, false>), grid, dim3(kBlock), 0, cfg.stream, L);
+      hipLaunchKernelGGL((fluid_lanes_kernel<T, GRAV, HSE, LIM, false, NU>), grid, dim3(kBlock), 0, cfg.stream, L);
   } else {
     constexpr int DD = D == 0 ? 1 : D;
-    hipLaunchKernelGGL((fluid_strided_kernel<T, DD, GRAV, HSE, LIM>), grid, dim3(kBlock), 0, cfg.stream, L);
+    hipLaunchKernelGGL((fluid_strided_kernel<T, DD, GRAV, HSE, LIM, NU>), grid, dim3(kBlock), 0, cfg.stream, L);
   }
 }
 
 template <typename T, int D, int LIM>
 void Engine::fluid_dispatch_lim() {
   if (!cfg.gravity)
-    launch_fluid<T, D, 0, false, LIM>();
+    launch_fluid_mesh<T, D, 0, false, LIM>();
   else if (cfg.gravity == 1)
-    cfg.hse ? launch_fluid<T, D, 1, true, LIM>() : launch_fluid<T, D, 1, false, LIM>();
+    cfg.hse ? launch_fluid_mesh<T, D, 1, true, LIM>() : launch_fluid_mesh<T, D, 1, false, LIM>();
   else
-    cfg.hse ? launch_fluid<T, D, 2, true, LIM>() : launch_fluid<T, D, 2, false, LIM>();
+    cfg.hse ? launch_fluid_mesh<T, D, 2, true, LIM>() : launch_fluid_mesh<T, D, 2, false, LIM>();
 }
 
 template <typename T, int D>
@@ -783,6 +794,16 @@ int Engine::fluid_dispatch() {
 
 template <typename T, int D, int LIM>
 int Engine::field_sweep_lim() {
+  if (nonuniform)
+    launch_field<T, D, LIM, true>();
+  else
+    launch_field<T, D, LIM, false>();
+  for (int f = 5; f < 8; ++f) cur[f] = 1 - cur[f];
+  return launch_check();
+}
+
+template <typename T, int D, int LIM, bool NU>
+void Engine::launch_field() {
   const int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
   FieldLaunch<T> L;
   L.rho = (const T*)pool[cur[0]][0].ptr;
@@ -793,23 +814,22 @@ int Engine::field_sweep_lim() {
   L.bto[0] = (T*)pool[1 - cur[5 + t1]][5 + t1].ptr;
   L.bto[1] = (T*)pool[1 - cur[5 + t2]][5 + t2].ptr;
   L.bdo = (T*)pool[1 - cur[5 + D]][5 + D].ptr;
+  for (int k = 0; k < 3; ++k) L.wid[k] = NU ? (const T*)wid[k].ptr : nullptr;
   L.wl = make_wl(this, K_FIELD_X + D);
   L.sc = (Scalars*)scal.ptr;
   if (L.wl.nwaves > 0) {
     const dim3 grid(grid_for((long long)L.wl.nwaves * 64));
     TimedLaunch tl(this, 2);
     if (D == 0) {
-      if (tuning.groups[K_FIELD_X])
+      if (tuning.groups[K_FIELD_X] && !NU)  // two positions per lane: uniform meshes only
         hipLaunchKernelGGL((field_lanes2_kernel<T, LIM>), grid, dim3(kBlock), 0, cfg.stream, L);
       else
-        hipLaunchKernelGGL((field_lanes_kernel<T, LIM>), grid, dim3(kBlock), 0, cfg.stream, L);
+        hipLaunchKernelGGL((field_lanes_kernel<T, LIM, NU>), grid, dim3(kBlock), 0, cfg.stream, L);
     } else {
       constexpr int DD = D == 0 ? 1 : D;
-      hipLaunchKernelGGL((field_strided_kernel<T, DD, LIM>), grid, dim3(kBlock), 0, cfg.stream, L);
+      hipLaunchKernelGGL((field_strided_kernel<T, DD, LIM, NU>), grid, dim3(kBlock), 0, cfg.stream, L);
     }
   }
-  for (int f = 5; f < 8; ++f) cur[f] = 1 - cur[f];
-  return launch_check();
 }
 
 template <typename T, int D>
@@ -841,6 +861,7 @@ int Engine::launch_check_cfl() {
   CheckLaunch<T> L;
   for (int k = 0; k < 5; ++k) L.u[k] = (const T*)pool[cur[k]][k].ptr;
   for (int k = 0; k < 3; ++k) L.b[k] = (const T*)pool[cur[5 + k]][5 + k].ptr;
+  for (int k = 0; k < 3; ++k) L.wid[k] = nonuniform ? (const T*)wid[k].ptr : nullptr;
   L.gamma = cfg.gamma;
   L.wl = make_wl(this, K_CHECK);
   L.sc = (Scalars*)scal.ptr;
@@ -856,6 +877,32 @@ int Engine::launch_check_cfl() {
   return launch_check();
 }
 
+// Irregular mesh (Sect. 2.5) of the single box at slot 0: the widths of its
+// cells along axis, converted to the storage precision.  The other axes keep
+// their uniform width until they are set too.
+template <typename T>
+int Engine::set_spacing_t(int axis, const double* widths) {
+  const HostBox& b = boxes[0];
+  for (int a = 0; a < 3; ++a) {
+    if (wid[a].ptr && (a != axis)) continue;
+    const int n = b.n[a];
+    std::vector<T> w(n);
+    for (int i = 0; i < n; ++i) w[i] = (T)(a == axis ? widths[i] : b.h[a]);
+    int rc = 0;
+    if (!wid[a].ptr && (rc = dev_alloc(wid[a], (size_t)n * sizeof(T)))) return rc;
+    HIP_TRY(hipMemcpyAsync(wid[a].ptr, w.data(), (size_t)n * sizeof(T), hipMemcpyHostToDevice, cfg.stream));
+    HIP_TRY(hipStreamSynchronize(cfg.stream));
+  }
+  nonuniform = true;
+  invalidate_graph();
+  return 0;
+}
+
+int Engine::set_spacing(int axis, const double* widths) {
+  if (boxes.empty() || !boxes[0].used) return fail(1, "no box");
+  return esize == 8 ? set_spacing_t<double>(axis, widths) : set_spacing_t<float>(axis, widths);
+}
+
 // The CFL speed of boxes just added (their step scalars start at zero): the
 // check kernel over the table without the reset; a box already fresh gets
 // its own value again (the same function of the same state).
@@ -867,6 +914,7 @@ int Engine::check_new() {
     CheckLaunch<double> L;
     for (int k = 0; k < 5; ++k) L.u[k] = (const double*)pool[cur[k]][k].ptr;
     for (int k = 0; k < 3; ++k) L.b[k] = (const double*)pool[cur[5 + k]][5 + k].ptr;
+    for (int k = 0; k < 3; ++k) L.wid[k] = nonuniform ? (const double*)wid[k].ptr : nullptr;
     L.gamma = cfg.gamma;
     L.wl = make_wl(this, K_CHECK);
     L.sc = (Scalars*)scal.ptr;
@@ -877,6 +925,7 @@ int Engine::check_new() {
     CheckLaunch<float> L;
     for (int k = 0; k < 5; ++k) L.u[k] = (const float*)pool[cur[k]][k].ptr;
     for (int k = 0; k < 3; ++k) L.b[k] = (const float*)pool[cur[5 + k]][5 + k].ptr;
+    for (int k = 0; k < 3; ++k) L.wid[k] = nonuniform ? (const float*)wid[k].ptr : nullptr;
     L.gamma = cfg.gamma;
     L.wl = make_wl(this, K_CHECK);
     L.sc = (Scalars*)scal.ptr;

@@ -155,7 +155,17 @@ int fish_strang_step(fish_ctx* c, double dt) {
 int fish_diagnostics(fish_ctx* c, double* out10) {
   if (!c || !out10) return c ? c->e.fail(FISH_ERR_ARG, "null output") : FISH_ERR_ARG;
   if (!c->e.boxes[c->slot].have_state) return c->e.fail(FISH_ERR_ARG, "no state");
+  if (c->e.nonuniform) return c->e.fail(FISH_ERR_UNSUPPORTED, "diagnostics on an irregular mesh");
   return c->e.diagnostics(c->slot, out10);
+}
+
+int fish_set_spacing(fish_ctx* c, int axis, const double* widths) {
+  if (!c) return FISH_ERR_ARG;
+  if (axis < 0 || axis > 2 || !widths) return c->e.fail(FISH_ERR_ARG, "bad axis or widths");
+  const int n = c->e.boxes[c->slot].n[axis];
+  for (int i = 0; i < n; ++i)
+    if (!(widths[i] > 0.0) || !std::isfinite(widths[i])) return c->e.fail(FISH_ERR_ARG, "widths must be finite and > 0");
+  return c->e.set_spacing(axis, widths);
 }
 
 int fish_autotune(fish_ctx* c, int reps, int32_t* targets_out) {

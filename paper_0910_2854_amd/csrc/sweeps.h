@@ -213,6 +213,7 @@ struct FluidArgs {
   T* uo[5];
   const T* b[3];
   const T* phi;
+  const T* wid[3];  // irregular mesh: cell widths per axis, else null
   Geo g;
   double gamma, alpha;
   int seg, nseg;   // strided: segment length along D and segments per pencil
@@ -227,6 +228,7 @@ struct FluidLaunch {
   T* uo[5];
   const T* b[3];
   const T* phi;
+  const T* wid[3];  // irregular mesh (one box): widths of the cells per axis
   double gamma, alpha;
   WorkList wl;
   Scalars* sc;
@@ -246,6 +248,8 @@ __device__ __forceinline__ FluidArgs<T> fluid_view(const FluidLaunch<T>& L, cons
 #pragma unroll
   for (int i = 0; i < 3; ++i) a.b[i] = L.b[i] + off;
   a.phi = L.phi ? L.phi + off : nullptr;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) a.wid[i] = L.wid[i];
   a.g = d.g;
   a.gamma = L.gamma;
   a.alpha = L.alpha;
@@ -268,6 +272,39 @@ __device__ __forceinline__ T load_phi(const T* phi, long long base, long long st
   }
   const T p0 = phi[base + (long long)(n - 1) * st], p1 = phi[base + (long long)(n - 2) * st];
   return p0 + (T)(s - (n - 1)) * (p0 - p1);
+}
+
+// ------------------------------------------------ irregular meshes (Sect. 2.5)
+// Width of the cell at stream index i along an axis, mapped as the cell is
+// (a ghost takes the width of the cell it copies or wraps to).
+template <typename T>
+__device__ __forceinline__ T width_at(const T* w, int i, int n, int bc) {
+  return w[map_cell(i, n, bc)];
+}
+// 1/(distance of the centres of the cells either side of a cell)
+template <typename T>
+__device__ __forceinline__ T inv_span(T wm, T w0, T wp) {
+  return rcp(T(0.5) * wm + w0 + T(0.5) * wp);
+}
+// Per-position factors of the fluid sweep from the widths of cells c-4 .. c
+// (w[0..4]): the predictor step of c-1 (dt/(2 dx)), the corrector step of c-3
+// (dt/dx), the weights dx_i/(dx_i-1 + dx_i) and dx_i/(dx_i + dx_i+1) that put
+// the limited slope of cell c-2 on its interfaces (the 1/2 of Eq. 34 on a
+// uniform mesh), and the inverse centre spans of c-1 and c-3 for gravity.
+template <typename T>
+struct FluidNU {
+  T kh1, kf3, wl2, wr2, isp1, isp3;
+};
+template <typename T>
+__device__ __forceinline__ FluidNU<T> fluid_nu(const T* w, T dt) {
+  FluidNU<T> n;
+  n.kh1 = T(0.5) * dt * rcp(w[3]);
+  n.kf3 = dt * rcp(w[1]);
+  n.wl2 = w[2] * rcp(w[1] + w[2]);
+  n.wr2 = w[2] * rcp(w[2] + w[3]);
+  n.isp1 = inv_span(w[2], w[3], w[4]);
+  n.isp3 = inv_span(w[0], w[1], w[2]);
+  return n;
 }
 
 template <typename T>
@@ -301,12 +338,14 @@ struct FluidHist {
 // GRAV: 0 none, 1 unsplit source in the predictor and corrector (Eqs. 41-43),
 // 2 split kicks G(dt/2) L G(dt/2) (Eqs. 38-40): the entering cell is kicked
 // by gh_c = (dt/2)(phi_c+1 - phi_c-1)/(2h), which the caller computes from
-// its own loads (the first positions of a stream have no history of phi),
-// before its first use; the output cell c-3 after its corrector, by the same
-// factor formed from the history of phi.
-template <typename T, int D, int GRAV, bool HSE, int LIM, typename H, bool RELOAD_U3>
+// its own loads for the cell the position maps to (the first positions of a
+// stream have no history of phi; a ghost is then the exact copy of its kicked
+// cell), before its first use; the output cell c-3 after its corrector, by
+// the same factor formed from the history of phi.
+// NU: irregular mesh, with the per-position factors in nu (uniform: k).
+template <typename T, int D, int GRAV, bool HSE, int LIM, typename H, bool RELOAD_U3, bool NU = false>
 __device__ __forceinline__ void fluid_position(const T* uc_in, const Vec<T, 3>& bcc, T phc, T gh_c,
-                                               const T* u3_loaded, const FluidConsts<T>& k,
+                                               const T* u3_loaded, const FluidConsts<T>& k, const FluidNU<T>& nu,
                                                const FluidHist<T, HSE>& hi, FluidHist<T, HSE>& ho, T* un) {
   T phm1 = T(0), phm2 = T(0), phm3 = T(0), phm4 = T(0);
   if (GRAV != 0 || HSE) {
@@ -331,16 +370,17 @@ __device__ __forceinline__ void fluid_position(const T* uc_in, const Vec<T, 3>& 
 #pragma unroll
   for (int i = 0; i < 5; ++i) F1.v[i] = T(0.5) * (q0m.F[i] + q0.F[i]) - k.halfalpha * Q[i];
   const Vec<T, 5> F1m = prev_vec<H>(F1, hi.F1, ho.F1);
-  // predictor half step of cell c-1 (Eq. 41)
+  // predictor half step of cell c-1 (Eq. 41; Eq. 37 on an irregular mesh)
   T up[5];
+  const T khalf = NU ? nu.kh1 : k.k_half;
   if (GRAV == 1) {
     T S[5];
-    gravity_source<T, D>(q0m.u[RHO], q0m.u[MX + D], phc - phm2, k.inv2h, S);
+    gravity_source<T, D>(q0m.u[RHO], q0m.u[MX + D], phc - phm2, NU ? nu.isp1 : k.inv2h, S);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) up[i] = q0m.u[i] - k.k_half * (F1.v[i] - F1m.v[i]) + k.half_dt * S[i];
+    for (int i = 0; i < 5; ++i) up[i] = q0m.u[i] - khalf * (F1.v[i] - F1m.v[i]) + k.half_dt * S[i];
   } else {
 #pragma unroll
-    for (int i = 0; i < 5; ++i) up[i] = q0m.u[i] - k.k_half * (F1.v[i] - F1m.v[i]);
+    for (int i = 0; i < 5; ++i) up[i] = q0m.u[i] - khalf * (F1.v[i] - F1m.v[i]);
   }
   // cell quantities of the half-step state of c-1 (field unchanged), and of c-2
   CellQ<T, HSE> q1;
@@ -363,18 +403,31 @@ __device__ __forceinline__ void fluid_position(const T* uc_in, const Vec<T, 3>& 
   // limited second-order flux at interface c-5/2 (Eq. 34); both limiters
   // taken here belong to cell c-2 (its half-step state decides the switch)
   const T sup2 = LIM == 2 ? H::prev(q1.sup, hi.sp1, ho.sp1) : T(0);
+  // (irregular mesh: each difference weighted to put cell c-2's slope on its
+  // interfaces, which absorbs the 1/2)
   Vec<T, 5> Lp, F2;
+  if (!NU) {
 #pragma unroll
-  for (int i = 0; i < 5; ++i) Lp.v[i] = limit_cell<T, LIM>(sup2, apm.v[i], ap.v[i]);
+    for (int i = 0; i < 5; ++i) Lp.v[i] = limit_cell<T, LIM>(sup2, apm.v[i], ap.v[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) Lp.v[i] = limit_cell<T, LIM>(sup2, nu.wl2 * apm.v[i], nu.wr2 * ap.v[i]);
+  }
   const Vec<T, 5> Lpm = prev_vec<H>(Lp, hi.Lp, ho.Lp);
+  if (!NU) {
 #pragma unroll
-  for (int i = 0; i < 5; ++i)
-    F2.v[i] = bsm.v[i] + T(0.5) * (Lpm.v[i] - limit_cell<T, LIM>(sup2, amm.v[i], am.v[i]));
+    for (int i = 0; i < 5; ++i)
+      F2.v[i] = bsm.v[i] + T(0.5) * (Lpm.v[i] - limit_cell<T, LIM>(sup2, amm.v[i], am.v[i]));
+  } else {
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+      F2.v[i] = bsm.v[i] + (Lpm.v[i] - limit_cell<T, LIM>(sup2, nu.wl2 * amm.v[i], nu.wr2 * am.v[i]));
+  }
   const Vec<T, 5> F2m = prev_vec<H>(F2, hi.F2, ho.F2);
   // state of cell c-3 before the sweep
   T u3[5];
   // kick of c-3 (split gravity): phi of c-2 and c-4
-  const T gh3 = GRAV == 2 ? k.half_dt * (phm2 - phm4) * k.inv2h : T(0);
+  const T gh3 = GRAV == 2 ? k.half_dt * (phm2 - phm4) * (NU ? nu.isp3 : k.inv2h) : T(0);
   if (RELOAD_U3) {
 #pragma unroll
     for (int i = 0; i < 5; ++i) u3[i] = u3_loaded[i];
@@ -389,18 +442,19 @@ __device__ __forceinline__ void fluid_position(const T* uc_in, const Vec<T, 3>& 
     for (int i = 0; i < 5; ++i) u3[i] = um3.v[i];
   }
   // corrector of cell c-3 (Eq. 43)
+  const T kfull = NU ? nu.kf3 : k.k_full;
   if (GRAV == 1) {
     const T rpm2 = H::prev(up[RHO], hi.rp1, ho.rp1);   // rho' of c-2
     const T rpm3 = H::prev(rpm2, hi.rp2, ho.rp2);      // rho' of c-3
     const T mpm2 = H::prev(up[MX + D], hi.mp1, ho.mp1);
     const T mpm3 = H::prev(mpm2, hi.mp2, ho.mp2);
     T S[5];
-    gravity_source<T, D>(rpm3, mpm3, phm2 - phm4, k.inv2h, S);
+    gravity_source<T, D>(rpm3, mpm3, phm2 - phm4, NU ? nu.isp3 : k.inv2h, S);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) un[i] = u3[i] - k.k_full * (F2.v[i] - F2m.v[i]) + k.dt * S[i];
+    for (int i = 0; i < 5; ++i) un[i] = u3[i] - kfull * (F2.v[i] - F2m.v[i]) + k.dt * S[i];
   } else {
 #pragma unroll
-    for (int i = 0; i < 5; ++i) un[i] = u3[i] - k.k_full * (F2.v[i] - F2m.v[i]);
+    for (int i = 0; i < 5; ++i) un[i] = u3[i] - kfull * (F2.v[i] - F2m.v[i]);
     if (GRAV == 2) gravity_kick<T, D>(un, gh3);
   }
   (void)phm3;
@@ -457,7 +511,7 @@ __device__ __forceinline__ bool strided_map(int wave, int nA, int nO, int nseg, 
 }
 
 // Strided policy (D = y or z): one lane per pencil segment, lanes along x.
-template <typename T, int D, int GRAV, bool HSE, int LIM>
+template <typename T, int D, int GRAV, bool HSE, int LIM, bool NU>
 __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidLaunch<T> L) {
   static_assert(D != 0, "x sweeps use the lanes policy");
   constexpr int A = 0;  // lanes walk along x
@@ -495,6 +549,7 @@ __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidLaunch<T> L) {
     T u[5];
     Vec<T, 3> bc;
     T phi, gh;
+    T w[5];  // irregular mesh: widths of cells c-4 .. c
   };
   // inputs of position it (loads only: issued one position ahead of use)
   auto load = [&](int it) {
@@ -511,15 +566,30 @@ __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidLaunch<T> L) {
     in.bc.v[T1] = T(0.5) * (ld(b1, base) + ld(b1, hi1));
     in.bc.v[T2] = T(0.5) * (ld(b2, base) + ld(b2, hi2));
     in.phi = GRAV ? load_phi(a.phi, lbase, stD, s, nD, bcD) : T(0);
-    in.gh = GRAV == 2 ? k.half_dt * (load_phi(a.phi, lbase, stD, s + 1, nD, bcD) -
-                                     load_phi(a.phi, lbase, stD, s - 1, nD, bcD)) * k.inv2h
-                      : T(0);
+    if (NU) {
+#pragma unroll
+      for (int j = 0; j < 5; ++j) in.w[j] = width_at(a.wid[D], s - 4 + j, nD, bcD);
+    }
+    if (GRAV == 2) {
+      // the kick of the cell this position maps to (a ghost is exactly the
+      // copy of its kicked cell)
+      const int sm = map_cell(s, nD, bcD);
+      const T isp0 = NU ? inv_span(width_at(a.wid[D], sm - 1, nD, bcD), width_at(a.wid[D], sm, nD, bcD),
+                                   width_at(a.wid[D], sm + 1, nD, bcD))
+                        : k.inv2h;
+      in.gh = k.half_dt * (load_phi(a.phi, lbase, stD, sm + 1, nD, bcD) -
+                           load_phi(a.phi, lbase, stD, sm - 1, nD, bcD)) * isp0;
+    } else {
+      in.gh = T(0);
+    }
     return in;
   };
   auto compute = [&](int it, const In& in, const FluidHist<T, HSE>& hi, FluidHist<T, HSE>& ho) {
     const int s = s0 - 3 + it;
     T un[5];
-    fluid_position<T, D, GRAV, HSE, LIM, StridedHist, false>(in.u, in.bc, in.phi, in.gh, nullptr, k, hi, ho, un);
+    const FluidNU<T> nu = NU ? fluid_nu(in.w, k.dt) : FluidNU<T>{};
+    fluid_position<T, D, GRAV, HSE, LIM, StridedHist, false, NU>(in.u, in.bc, in.phi, in.gh, nullptr, k, nu, hi, ho,
+                                                                  un);
     if (it >= 6 && s - 3 < s1 && active) {
       const long long o = (long long)(s - 3) * stD;
 #pragma unroll
@@ -576,6 +646,17 @@ __device__ __forceinline__ double cfl_of(const double* smax, const Geo& g) {
   return c;
 }
 
+// Eq. (42), the CFL condition on an irregular mesh: max over the active axes
+// of one cell's speed over its own width along that axis.
+__device__ __forceinline__ double cfl_of_cell(const double* sp, double wx, double wy, double wz, const Geo& g) {
+  const double w[3] = {wx, wy, wz};
+  double c = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (g.n[d] > 1) c = fmax(c, sp[d] / w[d]);
+  return c;
+}
+
 // Reduce (cmax, bad) over the wave and publish with one atomic per wave.
 // Every lane of the wave must reach this call.
 __device__ __forceinline__ void publish_cfl(double cmax, int bad, Scalars* sc) {
@@ -595,7 +676,7 @@ __device__ __forceinline__ void publish_cfl(double cmax, int bad, Scalars* sc) {
 // Lanes policy (D = x): each wave streams rows_per_wave whole x rows.  With
 // CFL the sweep also reduces the CFL speed of the state it writes (the last
 // sub-operator of a double step leaves the next step's time step ready).
-template <typename T, int GRAV, bool HSE, int LIM, bool CFL>
+template <typename T, int GRAV, bool HSE, int LIM, bool CFL, bool NU>
 __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
   constexpr int D = 0;
   const BoxDesc* d;
@@ -618,16 +699,19 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
   hA.zero();
   hB.zero();
   double smax[3] = {0.0, 0.0, 0.0};
+  double cnu = 0.0;  // irregular mesh: the CFL speed over widths, per cell
   int bad = 0;
   RowCursor rc;
   rc.init(lane, L, r0, rows, ny);
   unsigned base = 0, dy = 0, dz = 0;  // row offsets (elements; arrays < 2^31 elements)
+  T wy = T(1), wz = T(1);             // irregular mesh: widths of the row's cell in y, z
   constexpr unsigned z4 = sizeof(T);
   struct In {
     T u[5], u3[5];
     Vec<T, 3> bc;
     T phi, gh;
     T b3[3];      // cell-centred field of the output cell (CFL only)
+    T w[5], wy, wz;  // irregular mesh: widths of cells c-4 .. c along x; the row's y, z widths
     unsigned o3;  // byte offset of the output cell c-3
     int co;       // output cell index along x
     bool valid;
@@ -639,6 +723,10 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
       base = (unsigned)((long long)y * g.st[1] + (long long)z * g.st[2]);
       dy = (unsigned)((long long)(map_face_near(y + 1, ny, g.bc[1]) - y) * g.st[1]) * z4;
       dz = (unsigned)((long long)(map_face_near(z + 1, nz, g.bc[2]) - z) * g.st[2]) * z4;
+      if (NU) {
+        wy = width_at(a.wid[1], y, ny, g.bc[1]);
+        wz = width_at(a.wid[2], z, nz, g.bc[2]);
+      }
     }
     In in;
     in.valid = (it << 6) + lane < npos;
@@ -656,9 +744,24 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
     in.bc.v[1] = T(0.5) * (ld(a.b[1], ms) + ld(a.b[1], ms + dy));
     in.bc.v[2] = T(0.5) * (ld(a.b[2], ms) + ld(a.b[2], ms + dz));
     in.phi = GRAV ? load_phi(a.phi, (long long)base, 1, cpos, nx, g.bc[0]) : T(0);
-    in.gh = GRAV == 2 ? k.half_dt * (load_phi(a.phi, (long long)base, 1, cpos + 1, nx, g.bc[0]) -
-                                     load_phi(a.phi, (long long)base, 1, cpos - 1, nx, g.bc[0])) * k.inv2h
-                      : T(0);
+    if (NU) {
+#pragma unroll
+      for (int j = 0; j < 5; ++j) in.w[j] = width_at(a.wid[0], cpos - 4 + j, nx, g.bc[0]);
+      in.wy = wy;
+      in.wz = wz;
+    }
+    if (GRAV == 2) {
+      // the kick of the cell this position maps to (a ghost is exactly the
+      // copy of its kicked cell)
+      const int cm = map_cell(cpos, nx, g.bc[0]);
+      const T isp0 = NU ? inv_span(width_at(a.wid[0], cm - 1, nx, g.bc[0]), width_at(a.wid[0], cm, nx, g.bc[0]),
+                                   width_at(a.wid[0], cm + 1, nx, g.bc[0]))
+                        : k.inv2h;
+      in.gh = k.half_dt * (load_phi(a.phi, (long long)base, 1, cm + 1, nx, g.bc[0]) -
+                           load_phi(a.phi, (long long)base, 1, cm - 1, nx, g.bc[0])) * isp0;
+    } else {
+      in.gh = T(0);
+    }
     in.o3 = (base + (unsigned)map_cell_near(cpos - 3, nx, g.bc[0])) * z4;
 #pragma unroll
     for (int i = 0; i < 5; ++i) in.u3[i] = ld(a.u[i], in.o3);
@@ -674,7 +777,8 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
   };
   auto compute = [&](const In& in, const FluidHist<T, HSE>& hi, FluidHist<T, HSE>& ho) {
     T un[5];
-    fluid_position<T, D, GRAV, HSE, LIM, LaneHist, true>(in.u, in.bc, in.phi, in.gh, in.u3, k, hi, ho, un);
+    const FluidNU<T> nu = NU ? fluid_nu(in.w, k.dt) : FluidNU<T>{};
+    fluid_position<T, D, GRAV, HSE, LIM, LaneHist, true, NU>(in.u, in.bc, in.phi, in.gh, in.u3, k, nu, hi, ho, un);
     const bool out = in.valid && in.co >= 0 && in.co < nx;
     if (out) {
 #pragma unroll
@@ -685,8 +789,12 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
       double sp[3];
       cell_cfl_speeds<T>(un, in.b3, a.gamma, g, sp, cell_bad);
       if (out) {
+        if (NU) {
+          cnu = fmax(cnu, cfl_of_cell(sp, (double)in.w[1], (double)in.wy, (double)in.wz, g));
+        } else {
 #pragma unroll
-        for (int dd = 0; dd < 3; ++dd) smax[dd] = fmax(smax[dd], sp[dd]);
+          for (int dd = 0; dd < 3; ++dd) smax[dd] = fmax(smax[dd], sp[dd]);
+        }
         bad |= cell_bad;
       }
     }
@@ -698,7 +806,7 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
     cur = load(it + 2);
     compute(nxt, hB, hA);
   }
-  if (CFL) publish_cfl(cfl_of(smax, g), bad, const_cast<Scalars*>(a.sc));
+  if (CFL) publish_cfl(NU ? cnu : cfl_of(smax, g), bad, const_cast<Scalars*>(a.sc));
 }
 
 // ------------------------------------------------------------ B_d (fused)
@@ -716,6 +824,7 @@ struct FieldArgs {
   const T* bd;             // b_d (input)
   T* bto[2];               // outputs
   T* bdo;
+  const T* wid[3];         // irregular mesh: cell widths per axis, else null
   Geo g;
   int seg, nseg;           // strided policy
   int rows_per_wave;       // lanes policy
@@ -730,6 +839,7 @@ struct FieldLaunch {
   const T* bd;
   T* bto[2];
   T* bdo;
+  const T* wid[3];  // irregular mesh (one box): widths of the cells per axis
   WorkList wl;
   Scalars* sc;
 };
@@ -746,6 +856,8 @@ __device__ __forceinline__ FieldArgs<T> field_view(const FieldLaunch<T>& L, cons
   a.bto[0] = L.bto[0] + off;
   a.bto[1] = L.bto[1] + off;
   a.bdo = L.bdo + off;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) a.wid[i] = L.wid[i];
   a.g = d.g;
   const int D = KIND - K_FIELD_X;
   a.seg = d.par[KIND];
@@ -766,9 +878,17 @@ struct RowHist {
 // first-order upwind predictor flux, second-order limited upwind corrector
 // flux (end of Sect. 2.4), Eq. (63).  Gives the edge flux at d-face c-3 (the
 // interface between c-4 and c-3) and, for NEED_BN, the new b_t of cell c-4.
-template <typename T, int LIM, typename H, bool NEED_BN, bool RELOAD_B4>
-__device__ __forceinline__ T row_position(T w0, T bb, T b4_loaded, T k_half, T k_full, const RowHist<T>& hi,
-                                          RowHist<T>& ho, T& bn) {
+// Irregular mesh (Sect. 2.5): the weights that put the limited slopes of cells
+// c-4 (upwind side "up") and c-3 ("dn") on the interface between them, as in
+// the fluid corrector; k_half and k_full are then those of cells c-2 and c-4.
+template <typename T>
+struct FieldW {
+  T wl4, wr4, wl3, wr3;
+};
+
+template <typename T, int LIM, typename H, bool NEED_BN, bool RELOAD_B4, bool NU = false>
+__device__ __forceinline__ T row_position(T w0, T bb, T b4_loaded, T k_half, T k_full, const FieldW<T>& fw,
+                                          const RowHist<T>& hi, RowHist<T>& ho, T& bn) {
   const T w1 = H::prev(w0, hi.w1, ho.w1);
   const T w2 = H::prev(w1, hi.w2, ho.w2);
   // outer neighbours first: an odd face velocity gives exact negatives here
@@ -790,8 +910,14 @@ __device__ __forceinline__ T row_position(T w0, T bb, T b4_loaded, T k_half, T k
   const T fp3 = H::prev(fp2, hi.fp3, ho.fp3);
   const T fp4 = H::prev(fp3, hi.fp4, ho.fp4);
   const T fp5 = H::prev(fp4, hi.fp5, ho.fp5);
-  const T up = fp4 + T(0.5) * limit<T, LIM>(fp4 - fp5, fp3 - fp4);
-  const T dn = fp3 - T(0.5) * limit<T, LIM>(fp3 - fp4, fp2 - fp3);
+  T up, dn;
+  if (!NU) {
+    up = fp4 + T(0.5) * limit<T, LIM>(fp4 - fp5, fp3 - fp4);
+    dn = fp3 - T(0.5) * limit<T, LIM>(fp3 - fp4, fp2 - fp3);
+  } else {
+    up = fp4 + limit<T, LIM>(fw.wl4 * (fp4 - fp5), fw.wr4 * (fp3 - fp4));
+    dn = fp3 - limit<T, LIM>(fw.wl3 * (fp3 - fp4), fw.wr3 * (fp2 - fp3));
+  }
   const T P2c = V7 > T(0) ? up : dn;                // Phi2 at c-7/2
   if (NEED_BN) {
     const T P2 = H::prev(P2c, hi.P2, ho.P2);                // Phi2 at c-9/2
@@ -920,29 +1046,93 @@ __device__ __forceinline__ FieldIn<T> field_load(const T* md, const T* rho, cons
   return in;
 }
 
+// Irregular mesh: the factors of one face row set (fixed along the pencil):
+// per t-face the weights of its low and high cell in the interpolation of
+// Eq. (65) (each the other cell's width over their sum), and 1/width of the
+// thread's cell across t1 and t2 for Eq. (64).
+template <typename T>
+struct FieldRowNU {
+  T a[4][2];  // faces A (t1-face c1), B (c1+1), C (t2-face c2), D (c2+1): low, high
+  T ih1, ih2;
+};
+template <typename T>
+__device__ __forceinline__ FieldRowNU<T> field_row_nu(T w1m, T w10, T w1p, T w2m, T w20, T w2p) {
+  FieldRowNU<T> r;
+  const T sA = rcp(w1m + w10), sB = rcp(w10 + w1p), sC = rcp(w2m + w20), sD = rcp(w20 + w2p);
+  r.a[0][0] = w10 * sA;
+  r.a[0][1] = w1m * sA;
+  r.a[1][0] = w1p * sB;
+  r.a[1][1] = w10 * sB;
+  r.a[2][0] = w20 * sC;
+  r.a[2][1] = w2m * sC;
+  r.a[3][0] = w2p * sD;
+  r.a[3][1] = w20 * sD;
+  r.ih1 = rcp(w10);
+  r.ih2 = rcp(w20);
+  return r;
+}
+// Irregular mesh: the per-position factors from the widths of cells c-5 .. c-2.
+template <typename T>
+struct FieldPosNU {
+  T kh, kf;
+  FieldW<T> w;
+};
+template <typename T>
+__device__ __forceinline__ FieldPosNU<T> field_pos_nu(const T* w, T dt) {
+  FieldPosNU<T> f;
+  f.kh = T(0.5) * dt * rcp(w[3]);
+  f.kf = dt * rcp(w[1]);
+  f.w.wl4 = w[1] * rcp(w[0] + w[1]);
+  f.w.wr4 = w[1] * rcp(w[1] + w[2]);
+  f.w.wl3 = w[2] * rcp(w[1] + w[2]);
+  f.w.wr3 = w[2] * rcp(w[2] + w[3]);
+  return f;
+}
+// Eq. (65) on an irregular mesh: linear interpolation between the two cell
+// centres, two separate products (never fused, so the value is exactly odd
+// when the velocities and widths are mirrored).
+template <typename T>
+__device__ __forceinline__ T face_interp(T alo, T vlo, T ahi, T vhi) {
+  const T p = alo * vlo;
+  const T q = ahi * vhi;
+  return p + q;
+}
+
 // All four face rows at one position.
-template <typename T, int LIM, typename H, bool RELOAD_B4>
-__device__ __forceinline__ void field_compute(const FieldIn<T>& in, const FieldConsts<T>& k, const RowHist<T>* hi,
-                                              RowHist<T>* ho, T& bn1, T& bn2, T& dbd) {
+template <typename T, int LIM, typename H, bool RELOAD_B4, bool NU = false>
+__device__ __forceinline__ void field_compute(const FieldIn<T>& in, const FieldConsts<T>& k, const FieldRowNU<T>& rn,
+                                              const FieldPosNU<T>& pn, const RowHist<T>* hi, RowHist<T>* ho, T& bn1,
+                                              T& bn2, T& dbd) {
   // v_d of the five cells around the thread's pencil (Sect. 2.4: the fluid
   // state current at B_d)
   T v[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) v[i] = in.md[i] * rcp(in.rho[i]);
   // Eq. (65) on the four t-faces
-  const T wA = T(0.5) * (v[1] + v[0]), wB = T(0.5) * (v[0] + v[2]);
-  const T wC = T(0.5) * (v[3] + v[0]), wD = T(0.5) * (v[0] + v[4]);
+  T wA, wB, wC, wD;
+  if (!NU) {
+    wA = T(0.5) * (v[1] + v[0]);
+    wB = T(0.5) * (v[0] + v[2]);
+    wC = T(0.5) * (v[3] + v[0]);
+    wD = T(0.5) * (v[0] + v[4]);
+  } else {
+    wA = face_interp(rn.a[0][0], v[1], rn.a[0][1], v[0]);
+    wB = face_interp(rn.a[1][0], v[0], rn.a[1][1], v[2]);
+    wC = face_interp(rn.a[2][0], v[3], rn.a[2][1], v[0]);
+    wD = face_interp(rn.a[3][0], v[0], rn.a[3][1], v[4]);
+  }
+  const T kh = NU ? pn.kh : k.k_half, kf = NU ? pn.kf : k.k_full;
   T dummy;
-  const T eA = row_position<T, LIM, H, true, RELOAD_B4>(wA, in.b[0], in.b4a, k.k_half, k.k_full, hi[0], ho[0], bn1);
-  const T eB = row_position<T, LIM, H, false, false>(wB, in.b[1], T(0), k.k_half, k.k_full, hi[1], ho[1], dummy);
-  const T eC = row_position<T, LIM, H, true, RELOAD_B4>(wC, in.b[2], in.b4c, k.k_half, k.k_full, hi[2], ho[2], bn2);
-  const T eD = row_position<T, LIM, H, false, false>(wD, in.b[3], T(0), k.k_half, k.k_full, hi[3], ho[3], dummy);
+  const T eA = row_position<T, LIM, H, true, RELOAD_B4, NU>(wA, in.b[0], in.b4a, kh, kf, pn.w, hi[0], ho[0], bn1);
+  const T eB = row_position<T, LIM, H, false, false, NU>(wB, in.b[1], T(0), kh, kf, pn.w, hi[1], ho[1], dummy);
+  const T eC = row_position<T, LIM, H, true, RELOAD_B4, NU>(wC, in.b[2], in.b4c, kh, kf, pn.w, hi[2], ho[2], bn2);
+  const T eD = row_position<T, LIM, H, false, false, NU>(wD, in.b[3], T(0), kh, kf, pn.w, hi[3], ho[3], dummy);
   // Eq. (64), physical signs: d/dt b_d = d_t1 Phi^t1 + d_t2 Phi^t2
-  dbd = k.dt * ((eB - eA) * k.ih1 + (eD - eC) * k.ih2);
+  dbd = k.dt * ((eB - eA) * (NU ? rn.ih1 : k.ih1) + (eD - eC) * (NU ? rn.ih2 : k.ih2));
 }
 
 // Strided policy (d = y or z).
-template <typename T, int D, int LIM>
+template <typename T, int D, int LIM, bool NU>
 __global__ __launch_bounds__(256) void field_strided_kernel(FieldLaunch<T> FL) {
   static_assert(D != 0, "x sweeps use the lanes policy");
   constexpr int A = 0;
@@ -984,6 +1174,14 @@ __global__ __launch_bounds__(256) void field_strided_kernel(FieldLaunch<T> FL) {
     hB[q].zero();
   }
   const FieldLane l = field_lane<T>(base, ownc, oc, 0);  // lane byte offsets, fixed along the pencil
+  FieldRowNU<T> rn{};
+  if (NU) {
+    const T* w1 = a.wid[T1];
+    const T* w2 = a.wid[T2];
+    const int n1 = g.n[T1], n2 = g.n[T2], b1 = g.bc[T1], b2 = g.bc[T2];
+    rn = field_row_nu(width_at(w1, c1 - 1, n1, b1), width_at(w1, c1, n1, b1), width_at(w1, c1 + 1, n1, b1),
+                      width_at(w2, c2 - 1, n2, b2), width_at(w2, c2, n2, b2), width_at(w2, c2 + 1, n2, b2));
+  }
   auto load = [&](int it) {
     const int s = s0 - 4 + it;  // uniform
     const long long off = (long long)map_cell(s, nD, g.bc[D]) * stD;
@@ -992,7 +1190,14 @@ __global__ __launch_bounds__(256) void field_strided_kernel(FieldLaunch<T> FL) {
   auto compute = [&](int it, const FieldIn<T>& in, const RowHist<T>* hi, RowHist<T>* ho) {
     const int s = s0 - 4 + it;
     T bn1, bn2, dbd;
-    field_compute<T, LIM, StridedHist, false>(in, k, hi, ho, bn1, bn2, dbd);
+    FieldPosNU<T> pn{};
+    if (NU) {
+      T w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) w[j] = width_at(a.wid[D], s - 5 + j, nD, g.bc[D]);
+      pn = field_pos_nu(w, k.dt);
+    }
+    field_compute<T, LIM, StridedHist, false, NU>(in, k, rn, pn, hi, ho, bn1, bn2, dbd);
     if (it >= 8 && s - 4 < s1) {
       const long long ob = (long long)(s - 4) * stD;
       if (own1) st(a.bto[0] + ob, l.fA, bn1);
@@ -1019,7 +1224,7 @@ __global__ __launch_bounds__(256) void field_strided_kernel(FieldLaunch<T> FL) {
 // In FP32 the kernel needs a few registers more than three waves per SIMD
 // allow; capping it there (one spill and one reload per position) is faster
 // than running two waves (measured).
-template <typename T, int LIM>
+template <typename T, int LIM, bool NU>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
 void field_lanes_kernel(FieldLaunch<T> FL) {
   constexpr int D = 0;
@@ -1052,8 +1257,11 @@ void field_lanes_kernel(FieldLaunch<T> FL) {
   rc.init(lane, L, r0, rows, ry);
   RowOffsets ro;
   bool own1 = false, own2 = false;
+  FieldRowNU<T> rnr{};  // irregular mesh: the factors of the current row
   struct In {
     FieldIn<T> f;
+    FieldRowNU<T> rn;
+    T w[4];              // irregular mesh: widths of cells c-5 .. c-2 along x
     unsigned b4off, fo;  // byte offsets of cell c-4 and d-face c-3 in the row
     int cpos;
     bool valid, own1, own2;
@@ -1064,6 +1272,12 @@ void field_lanes_kernel(FieldLaunch<T> FL) {
       row_offsets(g, rc.y, rc.z, ro);  // y, z face rows
       own1 = rc.z < g.n[2];
       own2 = rc.y < g.n[1];
+      if (NU) {
+        const int n1 = g.n[1], n2 = g.n[2], b1 = g.bc[1], b2 = g.bc[2], y = rc.y, zc = rc.z;
+        rnr = field_row_nu(width_at(a.wid[1], y - 1, n1, b1), width_at(a.wid[1], y, n1, b1),
+                           width_at(a.wid[1], y + 1, n1, b1), width_at(a.wid[2], zc - 1, n2, b2),
+                           width_at(a.wid[2], zc, n2, b2), width_at(a.wid[2], zc + 1, n2, b2));
+      }
     }
     In in;
     in.valid = (it << 6) + lane < npos;
@@ -1088,12 +1302,18 @@ void field_lanes_kernel(FieldLaunch<T> FL) {
     in.f.b4a = ld(a.bt[0], in.b4off);
     in.f.b4c = ld(a.bt[1], in.b4off);
     in.fo = (ro.base + (unsigned)max(in.cpos - 3, 0)) * z;
+    if (NU) {
+      in.rn = rnr;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) in.w[j] = width_at(a.wid[0], in.cpos - 5 + j, nx, g.bc[0]);
+    }
     rc.advance(L, rows, ry);
     return in;
   };
   auto compute = [&](const In& in, const RowHist<T>* hi, RowHist<T>* ho) {
     T bn1, bn2, dbd;
-    field_compute<T, LIM, LaneHist, true>(in.f, k, hi, ho, bn1, bn2, dbd);
+    const FieldPosNU<T> pn = NU ? field_pos_nu(in.w, k.dt) : FieldPosNU<T>{};
+    field_compute<T, LIM, LaneHist, true, NU>(in.f, k, in.rn, pn, hi, ho, bn1, bn2, dbd);
     const int cb = in.cpos - 4;
     if (in.valid && cb >= 0 && cb < nx) {
       if (in.own1) st(a.bto[0], in.b4off, bn1);
@@ -1288,6 +1508,7 @@ template <typename T>
 struct CheckLaunch {
   const T* u[5];
   const T* b[3];
+  const T* wid[3];  // irregular mesh (one box), else null
   double gamma;
   WorkList wl;
   Scalars* sc;
@@ -1323,6 +1544,8 @@ __global__ __launch_bounds__(256) void check_cfl_kernel(CheckLaunch<T> L) {
   int y = (int)(r % n1);
   int zz = (int)(r / n1);
   double smax[3] = {0.0, 0.0, 0.0};
+  double cnu = 0.0;                      // irregular mesh: per-cell speeds over widths
+  const bool nu = L.wid[0] != nullptr;   // uniform across the launch
   int bad = 0;
   for (; c < c1; c += 64) {
     const unsigned s = (unsigned)x + (unsigned)y * st1 + (unsigned)zz * st2;
@@ -1339,8 +1562,12 @@ __global__ __launch_bounds__(256) void check_cfl_kernel(CheckLaunch<T> L) {
     if (!isfinite(bc[0]) || !isfinite(bc[1]) || !isfinite(bc[2])) bad = 1;
     double sp[3];
     cell_cfl_speeds<T>(uc, bc, L.gamma, g, sp, bad);
+    if (nu) {
+      cnu = fmax(cnu, cfl_of_cell(sp, (double)L.wid[0][x], (double)L.wid[1][y], (double)L.wid[2][zz], g));
+    } else {
 #pragma unroll
-    for (int dd = 0; dd < 3; ++dd) smax[dd] = fmax(smax[dd], sp[dd]);
+      for (int dd = 0; dd < 3; ++dd) smax[dd] = fmax(smax[dd], sp[dd]);
+    }
     x += 64;
     while (x >= n0) {
       x -= n0;
@@ -1350,7 +1577,7 @@ __global__ __launch_bounds__(256) void check_cfl_kernel(CheckLaunch<T> L) {
       }
     }
   }
-  publish_cfl(cfl_of(smax, g), bad, L.sc + d->slot);
+  publish_cfl(nu ? cnu : cfl_of(smax, g), bad, L.sc + d->slot);
 }
 
 // Per-box step scalars; one thread per box of the table.
