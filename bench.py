@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -61,12 +63,23 @@ def load_traffic(name, esize, cells):
     return rec.get("bytes_per_launch")
 
 
-def run_gpu(fish, torch, st, n, precision, steps, warmup, cfl, segment, autotune=True, limiter=1):
+def stretched_widths(n, amp, phase):
+    """Cell widths of an irregular mesh (Sect. 2.5) on [0, 1]: proportional to
+    1 + amp sin(2 pi x + phase), normalised to sum to 1."""
+    xi = (np.arange(n) + 0.5) / n
+    w = 1.0 + amp * np.sin(2 * np.pi * xi + phase)
+    return w / w.sum()
+
+
+def run_gpu(fish, torch, st, n, precision, steps, warmup, cfl, segment, autotune=True, limiter=1, stretch=0.0):
     """Time `steps` Strang steps (dt from the device CFL step) in segments of at
     most `segment` steps, each started from the initial state: the state is
     re-uploaded and synchronised before a segment's clock starts and checked
     after it stops, so every timed step advances a physically valid state."""
     box = fish.Box(*n, precision=precision, cfl=cfl, limiter=limiter)
+    if stretch:
+        for a in range(3):
+            box.set_spacing(a, stretched_widths(n[a], stretch, float(a)))
     box.set_state(st)
     tuned = box.autotune(reps=5) if autotune else None
     for _ in range(warmup):
@@ -505,6 +518,8 @@ def main():
                     help="box workload: van Leer (default), minmod, or the Mach switch of Sect. 2.2")
     ap.add_argument("--gravity", choices=("unsplit", "split"), default="unsplit",
                     help="sphere workload: unsplit source (default) or split kicks, Sect. 2.3")
+    ap.add_argument("--stretch", type=float, default=0.0,
+                    help="box workload on an irregular mesh: widths 1 + STRETCH sin(2 pi x + axis) (Sect. 2.5)")
     ap.add_argument("--boxes", type=int, default=2048)
     ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
     ap.add_argument("--single-sample", type=int, default=8, help="boxes per size for the single-box comparison")
@@ -556,7 +571,7 @@ def main():
     for prec in ("fp32",) + (() if args.no_fp64 else ("fp64",)):
         log(f"GPU {prec}: {args.warmup} warmup + {args.steps} timed steps")
         res[prec] = run_gpu(fish, torch, st, n, prec, args.steps, args.warmup, cfl, args.segment,
-                            autotune=not args.no_autotune, limiter=LIMITERS[args.limiter])
+                            autotune=not args.no_autotune, limiter=LIMITERS[args.limiter], stretch=args.stretch)
         r = res[prec]
         log(f"  {r['wall'] * 1e3 / args.steps:.3f} ms/step, fluid launch avg "
             f"{r['fluid_ms'] / max(1, r['fluid_launches']):.3f} ms, state_ok={r['state_ok']}")
@@ -567,7 +582,9 @@ def main():
     fluid_avg_s = r["fluid_ms"] / max(1, r["fluid_launches"]) * 1e-3
     bytes_fluid = ncell * 13 * esize  # reads rho, m, E and the three face fields; writes rho, m, E
     achieved = bytes_fluid / fluid_avg_s / 1e9
-    traffic = load_traffic("fluid_sweep_traffic_256.json", esize, ncell)
+    # the counters were taken on the default configuration's kernels only
+    default_kernels = args.limiter == "vanleer" and not args.stretch
+    traffic = load_traffic("fluid_sweep_traffic_256.json", esize, ncell) if default_kernels else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -591,6 +608,7 @@ def main():
             "limiter": {"vanleer": "van Leer", "minmod": "minmod",
                         "switch": "van Leer where subsonic, minmod where supersonic"}[args.limiter],
             "autotuned": r["tuned"],
+            "mesh": "uniform" if not args.stretch else f"irregular: widths 1 + {args.stretch} sin(2 pi x + axis), Sect. 2.5",
         },
         "latency_ms": {"p50": pct(r["step_ms"], 50), "p99": pct(r["step_ms"], 99)},
         "step_roofline": {"bytes_per_cell": 384, "achieved_GBs": value * 384 / 1e9, "peak_GBs": HBM_PEAK_GBS,

@@ -98,7 +98,9 @@ int fish_create(const fish_params* p, fish_ctx** out);
 /* Release the context and all its device memory.  NULL is a no-op. */
 void fish_destroy(fish_ctx* ctx);
 
-/* Message describing the last failure on ctx (never NULL). */
+/* Message describing the last failure on ctx (never NULL).  With ctx NULL:
+ * the message of the last fish_create or fish_batch_create that failed on
+ * the calling thread (its context no longer exists). */
 const char* fish_last_error(const fish_ctx* ctx);
 
 /* Upload a state (layouts above).  phi is required when gravity is on and

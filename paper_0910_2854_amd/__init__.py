@@ -122,6 +122,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    try:  # torch first: its HIP runtime is then the one the library resolves to, in every process
+        import torch  # noqa: F401
+    except ImportError:  # pragma: no cover - the library still runs with hipMalloc and raw streams
+        pass
     lib = ctypes.CDLL(path)
     P, d, vp = ctypes.POINTER, ctypes.c_double, ctypes.c_void_p
     lib.fish_create.argtypes = [P(Params), P(vp)]
@@ -267,7 +271,7 @@ class Box:
         h = ctypes.c_void_p()
         rc = lib.fish_create(ctypes.byref(p), ctypes.byref(h))
         if rc != FISH_OK:
-            raise FishError(rc, "fish_create failed")
+            raise FishError(rc, "fish_create failed: " + lib.fish_last_error(None).decode())
         self._h = h
 
     # ---------------------------------------------------------------- helpers
@@ -442,7 +446,7 @@ class Batch:
         h = ctypes.c_void_p()
         rc = lib.fish_batch_create(ctypes.byref(p), ctypes.byref(h))
         if rc != FISH_OK:
-            raise FishError(rc, "fish_batch_create failed")
+            raise FishError(rc, "fish_batch_create failed: " + lib.fish_last_error(None).decode())
         self._h = h
 
     def _check(self, rc):
@@ -558,7 +562,7 @@ class Server:
         h = ctypes.c_void_p()
         rc = lib.fish_server_create(ctypes.byref(p), int(chunk_steps), ctypes.byref(h))
         if rc != FISH_OK:
-            raise FishError(rc, "fish_server_create failed")
+            raise FishError(rc, "fish_server_create failed: " + lib.fish_last_error(None).decode())
         self._h = h
         self._live = {}   # tag -> (request, input arrays, output dict) kept alive until completion
         self._done = (ctypes.c_int64 * 4096)()

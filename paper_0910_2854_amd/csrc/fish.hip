@@ -44,9 +44,15 @@ double cmax_of(const Scalars& s) {
 
 }  // namespace
 
+namespace {
+// message of the last failed fish_create / fish_batch_create on this thread
+thread_local std::string g_create_err;
+}  // namespace
+
 extern "C" {
 
 // ------------------------------------------------------------ single box
+
 int fish_create(const fish_params* p, fish_ctx** out) {
   if (!out) return FISH_ERR_ARG;
   *out = nullptr;
@@ -81,6 +87,7 @@ int fish_create(const fish_params* p, fish_ctx** out) {
   int rc = c->e.init(cfg, ne, 1);
   if (!rc) rc = c->e.add_box(n, h, bc, p->cfl, &c->slot);
   if (rc) {
+    g_create_err = c->e.err;
     delete c;
     return rc;
   }
@@ -90,7 +97,10 @@ int fish_create(const fish_params* p, fish_ctx** out) {
 
 void fish_destroy(fish_ctx* c) { delete c; }
 
-const char* fish_last_error(const fish_ctx* c) { return c ? c->e.err.c_str() : "null context"; }
+const char* fish_last_error(const fish_ctx* c) {
+  if (c) return c->e.err.c_str();
+  return g_create_err.empty() ? "null context" : g_create_err.c_str();
+}
 
 size_t fish_device_bytes(const fish_ctx* c) { return c ? c->e.device_bytes : 0; }
 
@@ -278,6 +288,7 @@ int fish_batch_create(const fish_batch_params* p, fish_batch** out) {
     // graph capture needs a stream other than the null stream
     if (hipSetDevice(p->device) != hipSuccess ||
         hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking) != hipSuccess) {
+      g_create_err = "stream creation failed";
       delete b;
       return FISH_ERR_DEVICE;
     }
@@ -285,6 +296,7 @@ int fish_batch_create(const fish_batch_params* p, fish_batch** out) {
   }
   int rc = b->e.init(cfg, cap, p->max_boxes);
   if (rc) {
+    g_create_err = b->e.err;
     fish_batch_destroy(b);
     return rc;
   }
