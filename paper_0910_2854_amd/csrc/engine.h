@@ -170,7 +170,7 @@ class Engine {
   int autotune(int reps, int* chosen);
   int set_shape(int kind, int value);
   int set_graph(bool on);
-  int set_spacing(int axis, const double* widths);  // one box: irregular mesh along axis
+  int set_spacing(int slot, int axis, const double* widths);  // one box: irregular mesh along axis
 
  private:
   int ensure_stage(size_t bytes);
@@ -182,7 +182,7 @@ class Engine {
   int last_sweep_and_cfl();
   void invalidate_graph();
   template <typename T>
-  int set_spacing_t(int axis, const double* widths);
+  int set_spacing_t(int slot, int axis, const double* widths);
   void drop_retired_graphs();
   int build_lists();
   template <typename T>

@@ -877,12 +877,12 @@ int Engine::launch_check_cfl() {
   return launch_check();
 }
 
-// Irregular mesh (Sect. 2.5) of the single box at slot 0: the widths of its
+// Irregular mesh (Sect. 2.5) of an engine's single box: the widths of its
 // cells along axis, converted to the storage precision.  The other axes keep
 // their uniform width until they are set too.
 template <typename T>
-int Engine::set_spacing_t(int axis, const double* widths) {
-  const HostBox& b = boxes[0];
+int Engine::set_spacing_t(int slot, int axis, const double* widths) {
+  const HostBox& b = boxes[slot];
   for (int a = 0; a < 3; ++a) {
     if (wid[a].ptr && (a != axis)) continue;
     const int n = b.n[a];
@@ -898,9 +898,10 @@ int Engine::set_spacing_t(int axis, const double* widths) {
   return 0;
 }
 
-int Engine::set_spacing(int axis, const double* widths) {
-  if (boxes.empty() || !boxes[0].used) return fail(1, "no box");
-  return esize == 8 ? set_spacing_t<double>(axis, widths) : set_spacing_t<float>(axis, widths);
+int Engine::set_spacing(int slot, int axis, const double* widths) {
+  if (slot < 0 || slot >= (int)boxes.size() || !boxes[slot].used) return fail(1, "no box");
+  if (table_slots.size() > 1) return fail(5, "irregular meshes take a single box");
+  return esize == 8 ? set_spacing_t<double>(slot, axis, widths) : set_spacing_t<float>(slot, axis, widths);
 }
 
 // The CFL speed of boxes just added (their step scalars start at zero): the

@@ -175,7 +175,7 @@ int fish_set_spacing(fish_ctx* c, int axis, const double* widths) {
   const int n = c->e.boxes[c->slot].n[axis];
   for (int i = 0; i < n; ++i)
     if (!(widths[i] > 0.0) || !std::isfinite(widths[i])) return c->e.fail(FISH_ERR_ARG, "widths must be finite and > 0");
-  return c->e.set_spacing(axis, widths);
+  return c->e.set_spacing(c->slot, axis, widths);
 }
 
 int fish_autotune(fish_ctx* c, int reps, int32_t* targets_out) {
