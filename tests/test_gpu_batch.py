@@ -227,3 +227,35 @@ def test_empty_batch_and_server():
     assert srv.pump() == []
     assert srv.stats()["resident"] == 0
     srv.close()
+
+
+@pytest.mark.parametrize("mode", ["split_gravity_hse", "limiter_switch"])
+def test_batch_modes_match_each_box_alone_bitwise(mode):
+    """The gravity forms and the limiter switch run through the batch engine
+    too: each box of a batch gives bitwise what it gives alone (FP32)."""
+    import paper_0910_2854_amd as fish
+    print(f"batch {mode} vs alone fp32", flush=True)
+    if mode == "split_gravity_hse":
+        kw = dict(gravity="split", hse=True)
+        boxes = [((16, 16, 16), (OUTFLOW,) * 3, 11), ((20, 12, 10), (OUTFLOW,) * 3, 12),
+                 ((9, 30, 7), (OUTFLOW, PERIODIC, OUTFLOW), 13)]
+        make = lambda n, seed: fi.sphere_state(n, seed)  # noqa: E731
+    else:
+        kw = dict(limiter=fish.MACH_SWITCH)
+        boxes = [((16, 16, 16), (PERIODIC,) * 3, 14), ((24, 10, 12), (OUTFLOW,) * 3, 15)]
+        make = lambda n, seed: fi.random_fourier_state(n, seed=seed, mach=1.0, beta=2.0, kmax=2)  # noqa: E731
+    steps = 3
+    b = _batch("fp32", **kw)
+    ids = [b.add(make(n, seed), bc=bc) for n, bc, seed in boxes]
+    b.step(steps)
+    for (n, bc, seed), i in zip(boxes, ids):
+        got = b.get(i)
+        g = fish.Box(*n, precision="fp32", bc=bc, **kw)
+        g.set_state(make(n, seed))
+        for _ in range(steps):
+            g.strang_step(0.0)
+        ref = g.get_state()
+        g.close()
+        for k in FIELDS:
+            assert np.array_equal(got[k], ref[k]), (mode, n, k)
+    b.close()
