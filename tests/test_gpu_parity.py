@@ -87,12 +87,13 @@ def test_lane_shift_primitive():
     np.testing.assert_array_equal(out, expect)
 
 
-@pytest.mark.parametrize("case", range(len(CASES)))
+# van Leer and the Mach switch on every shape, minmod on a subset
+LIMITER_CASES = [(c, lim) for lim in (1, 2) for c in range(len(CASES))] + [(c, 0) for c in (0, 3, 5, 10)]
+
+
+@pytest.mark.parametrize("case,limiter", LIMITER_CASES)
 @pytest.mark.parametrize("op", ["L", "B"])
-@pytest.mark.parametrize("limiter", [1, 0, 2])
 def test_suboperator_parity_fp64(case, op, limiter):
-    if limiter == 0 and case not in (0, 3, 5, 10):
-        pytest.skip("minmod is covered on a subset of the shapes")
     n, bc, grav, hse, seed = CASES[case]
     st = _state(n, bc, grav, seed)
     kw = dict(bc=bc, gravity=grav, hse=hse, limiter=limiter)
