@@ -129,6 +129,19 @@ int fish_cfl_dt(fish_ctx* ctx, double* dt_out);
  * Asynchronous. */
 int fish_strang_step(fish_ctx* ctx, double dt);
 
+/* CFL-stepped double steps until the box's time reaches t_end, with no host
+ * round trip per step: the device clamps each step, dt = min(k/C, (t_end -
+ * t)/2), so that the last one lands on t_end exactly (the steps a host loop
+ * of fish_cfl_dt and fish_strang_step with that clamp would take, bitwise),
+ * and takes dt = 0 once t_end is reached.  The steps run in chunks sized
+ * from the current CFL step, as captured graph replays when the context has a
+ * stream of its own (eager launches on the null stream); the host reads the
+ * step scalars once per chunk.  At most max_steps double steps are enqueued.
+ * *steps_taken (may be NULL) gets the double steps taken with dt > 0, *t_out
+ * (may be NULL) the time reached.  FISH_ERR_STATE if the state went bad on
+ * the way (the box stops, as in fish_strang_step).  Synchronises. */
+int fish_advance_to(fish_ctx* ctx, double t_end, int max_steps, int* steps_taken, double* t_out);
+
 /* One sub-operator for testing: op 0 = fluid L_dir, op 1 = field B_dir,
  * dir 0/1/2 = x/y/z, of size dt > 0.  Asynchronous. */
 int fish_sweep(fish_ctx* ctx, int op, int dir, double dt);

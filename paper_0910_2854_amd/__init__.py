@@ -98,7 +98,8 @@ EXPORTS = ("fish_create", "fish_destroy", "fish_last_error", "fish_set_state", "
            "fish_batch_remove", "fish_batch_get", "fish_batch_box_info", "fish_batch_step",
            "fish_batch_use_graph", "fish_batch_autotune", "fish_batch_sync", "fish_batch_timing_enable",
            "fish_batch_timing_read", "fish_set_shape", "fish_batch_set_shape", "fish_server_create", "fish_server_destroy", "fish_server_last_error",
-           "fish_server_batch", "fish_server_submit", "fish_server_pump", "fish_server_stats", "fish_set_spacing")
+           "fish_server_batch", "fish_server_submit", "fish_server_pump", "fish_server_stats", "fish_set_spacing",
+           "fish_advance_to")
 KERNEL_FLUID, KERNEL_FIELD, KERNEL_CHECK = 1, 2, 8
 KINDS = ("fluid_x", "fluid_y", "fluid_z", "field_x", "field_y", "field_z", "check")
 
@@ -171,6 +172,7 @@ def load_library(path: str = LIB_PATH):
     lib.fish_batch_timing_read.argtypes = [vp, P(ctypes.c_int), P(d)]
     lib.fish_set_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int32]
     lib.fish_set_spacing.argtypes = [vp, ctypes.c_int, P(ctypes.c_double)]
+    lib.fish_advance_to.argtypes = [vp, d, ctypes.c_int, P(ctypes.c_int), P(d)]
     lib.fish_set_spacing.restype = ctypes.c_int
     lib.fish_batch_set_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int32]
     lib.fish_set_shape.restype = ctypes.c_int
@@ -351,6 +353,14 @@ class Box:
         out = np.zeros(10)
         self._check(self._lib.fish_diagnostics(self._h, _dptr(out)))
         return _diag_dict(out)
+
+    def advance_to(self, t_end, max_steps=1 << 30):
+        """CFL-stepped double steps to time t_end, device-resident; returns
+        (double steps taken, time reached)."""
+        n = ctypes.c_int()
+        t = ctypes.c_double()
+        self._check(self._lib.fish_advance_to(self._h, float(t_end), int(max_steps), ctypes.byref(n), ctypes.byref(t)))
+        return n.value, t.value
 
     def set_spacing(self, axis, widths):
         """Irregular mesh (Sect. 2.5): the widths of the cells along axis."""

@@ -165,6 +165,7 @@ class Engine {
   int check_new();
   int strang_step(double dt);               // every box of the table
   int steps(int nsteps);                    // CFL-stepped double steps, graph when enabled
+  int advance_to(int slot, double t_end, int max_steps, int* taken, double* t_out);
   int sweep(int slot, int op, int dir, double dt);
   int diagnostics(int slot, double* out10);
   int autotune(int reps, int* chosen);

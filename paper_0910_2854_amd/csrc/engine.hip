@@ -640,6 +640,22 @@ static long long kind_waves(const HostBox& b, int kind, int target, int groups, 
   }
 }
 
+// A box alone in its engine at a default work shape: halve the shape while
+// the box fills fewer than 2048 waves (8 per CU), down to one row per wave
+// (x kinds), 8-cell segments (y/z kinds) or 64 cells per wave (check).  The
+// default suits a 256^3 box; a small box alone would leave most of the chip
+// idle.  A batch fills the chip with its many boxes, and a shape set by
+// fish_set_shape or the autotuner is used as set.
+static int single_box_target(const HostBox& b, int kind, int target, int groups) {
+  int lo = 1;
+  if (kind == K_FLUID_X) lo = b.n[0] + 6;
+  if (kind == K_FIELD_X) lo = b.n[0] + 8;
+  if (kind == K_FLUID_Y || kind == K_FLUID_Z || kind == K_FIELD_Y || kind == K_FIELD_Z) lo = 8;
+  int par = 1;
+  while (target / 2 >= lo && kind_waves(b, kind, target, groups, &par) < 2048) target /= 2;
+  return target;
+}
+
 int Engine::build_lists() {
   std::vector<int> slots;
   for (int s = 0; s < (int)boxes.size(); ++s)
@@ -660,9 +676,12 @@ int Engine::build_lists() {
     d.off = b.off;
     d.cfl = b.cfl;
     d.slot = slots[t];
+    const Tuning defaults = default_tuning();
     for (int k = 0; k < K_NUM; ++k) {
       int par = 1;
-      const long long w = kind_waves(b, k, tuning.target[k], tuning.groups[k], &par);
+      int target = tuning.target[k];
+      if (nb == 1 && target == defaults.target[k]) target = single_box_target(b, k, target, tuning.groups[k]);
+      const long long w = kind_waves(b, k, target, tuning.groups[k], &par);
       if ((long long)list[k].size() + w >= (1ll << 31) / 64)
         return fail(5, "work list exceeds the launch size");
       d.wave0[k] = (int)list[k].size();
@@ -1094,6 +1113,50 @@ int Engine::steps(int nsteps) {
     graph_ok = true;
   }
   for (int i = 0; i < nsteps; ++i) HIP_TRY(hipGraphLaunch(gexec, cfg.stream));
+  return 0;
+}
+
+// CFL-stepped double steps of one box (an engine with one box) until its time
+// reaches t_end: the device clamps each step so that the last lands on t_end
+// and later ones take dt = 0 (exact no-ops).  Steps run in chunks sized from
+// the current CFL step, as captured replays on a stream of the caller's (the
+// null stream cannot be captured: eager launches there); the host reads the
+// step scalars once per chunk.
+int Engine::advance_to(int slot, double t_end, int max_steps, int* taken, double* t_out) {
+  int rc = set_device();
+  if (rc) return rc;
+  if ((rc = ensure_table())) return rc;
+  if (table_slots.size() != 1) return fail(5, "advance_to takes an engine with one box");
+  if (!boxes[slot].cfl_fresh && (rc = check_cfl_all())) return rc;
+  Scalars s;
+  if ((rc = read_scalars(slot, &s))) return rc;
+  const int taken0 = s.taken;
+  hipLaunchKernelGGL(set_end_kernel, dim3(1), dim3(1), 0, cfg.stream, (Scalars*)scal.ptr + slot, t_end, 1);
+  if ((rc = launch_check())) return rc;
+  const bool graph_was = use_graph;
+  use_graph = timing_mask == 0 && cfg.stream != nullptr;  // the null stream cannot be captured
+  int done = 0;
+  while (done < max_steps && !s.status && s.t < t_end) {
+    // remaining double steps at the current CFL step, plus one for the landing
+    double cm;
+    std::memcpy(&cm, &s.cmax_bits, sizeof cm);
+    const double dt = cm > 0.0 ? boxes[slot].cfl / cm : 0.0;
+    double est = dt > 0.0 ? (t_end - s.t) / (2.0 * dt) + 1.0 : 1.0;
+    const int k = (int)std::min<double>({est, 64.0, (double)(max_steps - done)});
+    if ((rc = steps(std::max(1, k)))) break;
+    done += std::max(1, k);
+    if ((rc = read_scalars(slot, &s))) break;
+  }
+  use_graph = graph_was;
+  if (!graph_was) invalidate_graph();
+  hipLaunchKernelGGL(set_end_kernel, dim3(1), dim3(1), 0, cfg.stream, (Scalars*)scal.ptr + slot, 0.0, 0);
+  int rc2 = launch_check();
+  if (!rc && !rc2) rc2 = read_scalars(slot, &s);
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (taken) *taken = s.taken - taken0;
+  if (t_out) *t_out = s.t;
+  if (s.status) return fail(4, "the state went bad (rho <= 0, p <= 0 or a non-finite value)");
   return 0;
 }
 

@@ -162,6 +162,13 @@ int fish_strang_step(fish_ctx* c, double dt) {
   return c->e.strang_step(dt);
 }
 
+int fish_advance_to(fish_ctx* c, double t_end, int max_steps, int* steps_taken, double* t_out) {
+  if (!c) return FISH_ERR_ARG;
+  if (!std::isfinite(t_end) || max_steps < 0) return c->e.fail(FISH_ERR_ARG, "t_end must be finite, max_steps >= 0");
+  if (!c->e.boxes[c->slot].have_state) return c->e.fail(FISH_ERR_ARG, "no state");
+  return c->e.advance_to(c->slot, t_end, max_steps, steps_taken, t_out);
+}
+
 int fish_diagnostics(fish_ctx* c, double* out10) {
   if (!c || !out10) return c ? c->e.fail(FISH_ERR_ARG, "null output") : FISH_ERR_ARG;
   if (!c->e.boxes[c->slot].have_state) return c->e.fail(FISH_ERR_ARG, "no state");

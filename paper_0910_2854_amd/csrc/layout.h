@@ -15,8 +15,11 @@ struct Geo {
 struct Scalars {
   double dt;                    // step size of every sub-operator
   double t;                     // simulation time
+  double t_end;                 // with has_end: the CFL step is clamped to land on t_end
   unsigned long long cmax_bits; // max CFL speed (FP64 bits; all values >= 0)
   int status;                   // sticky: 1 = bad state seen
+  int has_end;
+  int taken;                    // double steps taken with dt > 0
   int pad;
 };
 

@@ -1597,23 +1597,40 @@ __global__ void finalize_dt_kernel(const BoxDesc* boxes, int nb, Scalars* sc) {
     s->dt = 0.0;
     return;
   }
-  s->dt = boxes[i].cfl / cmax;
+  double dt = boxes[i].cfl / cmax;
+  if (s->has_end) {
+    // the double step advances 2 dt: no further than t_end (a step of
+    // (t_end - t)/2 lands on t_end exactly), none once it is reached
+    const double rest = s->t_end - s->t;
+    dt = rest > 0.0 ? fmin(dt, 0.5 * rest) : 0.0;
+  }
+  s->dt = dt;
 }
 
 __global__ void advance_time_kernel(const BoxDesc* boxes, int nb, Scalars* sc) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nb) {
     Scalars* s = sc + boxes[i].slot;
-    s->t += 2.0 * s->dt;
+    if (s->dt > 0.0) {
+      s->t += 2.0 * s->dt;
+      s->taken += 1;
+    }
   }
 }
 
 __global__ void set_dt_kernel(Scalars* sc, double dt) { sc->dt = dt; }
+__global__ void set_end_kernel(Scalars* sc, double t_end, int on) {
+  sc->t_end = t_end;
+  sc->has_end = on;
+}
 __global__ void set_scalars_kernel(Scalars* sc, double t, int status) {
   sc->t = t;
   sc->status = status;
   sc->cmax_bits = 0ull;
   sc->dt = 0.0;
+  sc->t_end = 0.0;
+  sc->has_end = 0;
+  sc->taken = 0;
 }
 
 // ------------------------------------------------------------ diagnostics

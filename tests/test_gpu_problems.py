@@ -320,3 +320,47 @@ def test_polytrope_hse_keeps_the_centre():
     print("  final", final, flush=True)
     assert final[(64, True)] > final[(64, False)] and final[(128, True)] > final[(128, False)], final
     assert final[(128, False)] > final[(64, False)] and final[(128, True)] > final[(64, True)], final
+
+
+# ------------------------------------------------- device-resident end time
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("problem", ["rotor", "box"])
+def test_advance_to_matches_the_host_loop_bitwise(problem, prec):
+    """fish_advance_to clamps dt = min(k/C, (t_end - t)/2) on the device: the
+    same steps, bitwise, as the host loop of the validation tests, landing on
+    t_end exactly; max_steps bounds it; afterwards steps are unclamped."""
+    import paper_0910_2854_amd as fish
+    print(f"advance_to {problem} {prec}", flush=True)
+    if problem == "rotor":
+        st, s = fi.rotor_state(64)
+        T = 0.05
+        mk = lambda: _box(s, prec)  # noqa: E731
+    else:
+        st = fi.random_fourier_state((24, 20, 16), seed=3, mach=0.5, beta=5.0, kmax=2)
+        T = 0.02
+        stream = torch.cuda.Stream().cuda_stream if prec == "fp32" else None  # a caller stream: graph replays
+        mk = lambda: fish.Box(24, 20, 16, precision=prec, stream=stream)  # noqa: E731
+    a = mk()
+    a.set_state(st)
+    t_host, k_host = evolve(a, 0.0, T)
+    b = mk()
+    b.set_state(st)
+    k_dev, t_dev = b.advance_to(T)
+    assert (k_dev, t_dev) == (k_host, t_host) and t_dev == T, (k_dev, t_dev, k_host, t_host)
+    sa, sb = a.get_state(), b.get_state()
+    for k in FIELDS:
+        assert np.array_equal(sa[k], sb[k]), k
+    # unclamped afterwards: the next device step equals a host CFL step
+    a.strang_step(a.cfl_dt())
+    b.strang_step(0.0)
+    sa, sb = a.get_state(), b.get_state()
+    for k in FIELDS:
+        assert np.array_equal(sa[k], sb[k]), k
+    a.close()
+    # max_steps
+    c = mk()
+    c.set_state(st)
+    k3, t3 = c.advance_to(10 * T, max_steps=3)
+    assert k3 == 3 and t3 < 10 * T
+    c.close()
+    b.close()
