@@ -61,16 +61,35 @@ __device__ __forceinline__ bool work_item(const WorkList& wl, const BoxDesc*& d,
 }
 
 // ------------------------------------------------------------ addressing
+// A pointer every lane of the wave holds (a stream position of the strided
+// sweeps), pinned to scalar registers.  Without the pin the compiler folds the
+// per-lane offset into the loop-invariant part of the address and pays a
+// 64-bit vector add per load; pinned, the loads take the scalar base + 32-bit
+// lane offset form.  The asm is empty: it only names the register class.
+template <typename P>
+__device__ __forceinline__ P in_sgpr(P p) {
+  asm("" : "+s"(p));
+  return p;
+}
+
 // Load/store at a wave-uniform base pointer plus a 32-bit per-lane byte
 // offset (the scalar-base + vector-offset form of the global memory
-// instructions: no 64-bit address arithmetic per lane).
+// instructions: no 64-bit address arithmetic per lane).  The form needs the
+// offset's zero extension in the block of the access; the empty asm on the
+// offset keeps the compiler from extending a loop-invariant offset once before
+// the loop, which would leave a 64-bit vector add per access inside it.  Every
+// array the kernels touch is global memory: the address-space cast keeps the
+// global form when the compiler cannot see where a pointer came from.
+#define FISH_GLOBAL __attribute__((address_space(1)))
 template <typename T>
 __device__ __forceinline__ T ld(const T* p, unsigned off_bytes) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + off_bytes);
+  asm("" : "+v"(off_bytes));
+  return *(const FISH_GLOBAL T*)((const FISH_GLOBAL char*)p + off_bytes);
 }
 template <typename T>
 __device__ __forceinline__ void st(T* p, unsigned off_bytes, T v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + off_bytes) = v;
+  asm("" : "+v"(off_bytes));
+  *(FISH_GLOBAL T*)((FISH_GLOBAL char*)p + off_bytes) = v;
 }
 
 // ------------------------------------------------------------ position history
@@ -557,11 +576,11 @@ __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidLaunch<T> L) {
     const int s = s0 - 3 + it;  // uniform
     const long long off = (long long)map_cell(s, nD, bcD) * stD;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) in.u[i] = ld(a.u[i] + off, base);
-    const T* bD0 = a.b[D] + (long long)map_face(s, nD, bcD) * stD;
-    const T* bD1 = a.b[D] + (long long)map_face(s + 1, nD, bcD) * stD;
-    const T* b1 = a.b[T1] + off;
-    const T* b2 = a.b[T2] + off;
+    for (int i = 0; i < 5; ++i) in.u[i] = ld(in_sgpr(a.u[i] + off), base);
+    const T* bD0 = in_sgpr(a.b[D] + (long long)map_face(s, nD, bcD) * stD);
+    const T* bD1 = in_sgpr(a.b[D] + (long long)map_face(s + 1, nD, bcD) * stD);
+    const T* b1 = in_sgpr(a.b[T1] + off);
+    const T* b2 = in_sgpr(a.b[T2] + off);
     in.bc.v[D] = T(0.5) * (ld(bD0, base) + ld(bD1, base));
     in.bc.v[T1] = T(0.5) * (ld(b1, base) + ld(b1, hi1));
     in.bc.v[T2] = T(0.5) * (ld(b2, base) + ld(b2, hi2));
@@ -593,7 +612,7 @@ __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidLaunch<T> L) {
     if (it >= 6 && s - 3 < s1 && active) {
       const long long o = (long long)(s - 3) * stD;
 #pragma unroll
-      for (int i = 0; i < 5; ++i) st(a.uo[i] + o, base, un[i]);
+      for (int i = 0; i < 5; ++i) st(in_sgpr(a.uo[i] + o), base, un[i]);
     }
   };
   // positions s0-3 .. s1+2, padded to an even count (the pad writes nothing;
@@ -1185,7 +1204,8 @@ __global__ __launch_bounds__(256) void field_strided_kernel(FieldLaunch<T> FL) {
   auto load = [&](int it) {
     const int s = s0 - 4 + it;  // uniform
     const long long off = (long long)map_cell(s, nD, g.bc[D]) * stD;
-    return field_load<T>(a.md + off, a.rho + off, a.bt[0] + off, a.bt[1] + off, l);
+    return field_load<T>(in_sgpr(a.md + off), in_sgpr(a.rho + off), in_sgpr(a.bt[0] + off), in_sgpr(a.bt[1] + off),
+                         l);
   };
   auto compute = [&](int it, const FieldIn<T>& in, const RowHist<T>* hi, RowHist<T>* ho) {
     const int s = s0 - 4 + it;
@@ -1200,13 +1220,13 @@ __global__ __launch_bounds__(256) void field_strided_kernel(FieldLaunch<T> FL) {
     field_compute<T, LIM, StridedHist, false, NU>(in, k, rn, pn, hi, ho, bn1, bn2, dbd);
     if (it >= 8 && s - 4 < s1) {
       const long long ob = (long long)(s - 4) * stD;
-      if (own1) st(a.bto[0] + ob, l.fA, bn1);
-      if (own2) st(a.bto[1] + ob, l.fA, bn2);
+      if (own1) st(in_sgpr(a.bto[0] + ob), l.fA, bn1);
+      if (own2) st(in_sgpr(a.bto[1] + ob), l.fA, bn2);
     }
     const int fd = s - 3;
     if (ownd && it >= 7 && (fd < s1 || (last && outD && fd == nD))) {
       const long long of = (long long)fd * stD;
-      st(a.bdo + of, l.fA, ld(a.bd + of, l.fA) + dbd);
+      st(in_sgpr(a.bdo + of), l.fA, ld(in_sgpr(a.bd + of), l.fA) + dbd);
     }
   };
   // positions s0-4 .. s1+3, padded to an even count (the pad writes nothing).
