@@ -105,6 +105,8 @@ struct StridedHist {
   }
 };
 
+// Lane shift with a carry across iterations (the two-positions-per-lane B_x
+// kernel, which keeps its history from one iteration to the next).
 __device__ __forceinline__ int lane_prev_bits(int cur, int& carry) {
   // wave_shr:1 -- lane i takes lane i-1; lane 0 keeps `old` = carry (whose
   // lane 0 holds lane 63 of the previous iteration); then carry = wave_ror:1.
@@ -128,32 +130,42 @@ __device__ __forceinline__ double lane_prev(double cur, double& carry) {
   return __longlong_as_double(((long long)ohi << 32) | (unsigned int)olo);
 }
 
-struct LaneHist {
+// Lanes policy without a carry: lane i takes lane i-1 by one DPP shift and
+// lane 0 takes zero.  The caller makes the wave's first lanes a halo that
+// recomputes the positions the previous iteration ended on, so nothing has
+// to cross from one iteration to the next and no history is kept.
+__device__ __forceinline__ float lane_shr(float cur) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(cur), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double lane_shr(double cur) {
+  const long long cb = __double_as_longlong(cur);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(cb & 0xffffffffll), 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(cb >> 32), 0x138, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+struct LaneShift {
   template <typename T>
-  __device__ __forceinline__ static T prev(const T& cur, const T& hin, T& hout) {
-    T c = hin;
-    const T o = lane_prev(cur, c);
-    hout = c;
-    return o;
+  __device__ __forceinline__ static T prev(const T& cur, const T&, T&) {
+    return lane_shr(cur);
   }
   template <typename T, bool HSE>
-  __device__ __forceinline__ static CellQ<T, HSE> prev(const CellQ<T, HSE>& cur, const CellQ<T, HSE>& hin,
-                                                       CellQ<T, HSE>& hout) {
+  __device__ __forceinline__ static CellQ<T, HSE> prev(const CellQ<T, HSE>& cur, const CellQ<T, HSE>&,
+                                                       CellQ<T, HSE>&) {
     CellQ<T, HSE> o;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      o.u[k] = prev(cur.u[k], hin.u[k], hout.u[k]);
-      o.F[k] = prev(cur.F[k], hin.F[k], hout.F[k]);
+      o.u[k] = lane_shr(cur.u[k]);
+      o.F[k] = lane_shr(cur.F[k]);
     }
-    o.d = prev(cur.d, hin.d, hout.d);
+    o.d = lane_shr(cur.d);
     if (HSE) {
-      o.vd = prev(cur.vd, hin.vd, hout.vd);
-      o.cF = prev(cur.cF, hin.cF, hout.cF);
-      o.cS = prev(cur.cS, hin.cS, hout.cS);
-      o.xiE = prev(cur.xiE, hin.xiE, hout.xiE);
+      o.vd = lane_shr(cur.vd);
+      o.cF = lane_shr(cur.cF);
+      o.cS = lane_shr(cur.cS);
+      o.xiE = lane_shr(cur.xiE);
     } else {
       o.vd = o.cF = o.cS = o.xiE = T(0);
-      hout.vd = hout.cF = hout.cS = hout.xiE = T(0);
     }
     return o;
   }
@@ -712,16 +724,19 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
   if (r0 >= nrows) return;  // whole wave exits together
   const int rows = (int)min((long long)a.rows_per_wave, nrows - r0);
   const int npos = rows * L;
-  const int nit = (npos + 63) >> 6;
+  // lanes 0..HALO-1 recompute the last positions of the previous iteration:
+  // the output of lane i depends on lanes i-6 .. i (the corrector's flux
+  // difference, the limited slopes, the relaxed differences, the predictor
+  // and its fluxes each reach one position back), so lanes 6..63 are exact
+  constexpr int HALO = 6, STEP = 64 - HALO;
+  const int nit = (npos + STEP - 1) / STEP;
   const FluidConsts<T> k = fluid_consts(a, D);
-  FluidHist<T, HSE> hA, hB;
-  hA.zero();
-  hB.zero();
+  FluidHist<T, HSE> hA, hB;  // unused by the carry-free policy
   double smax[3] = {0.0, 0.0, 0.0};
   double cnu = 0.0;  // irregular mesh: the CFL speed over widths, per cell
   int bad = 0;
   RowCursor rc;
-  rc.init(lane, L, r0, rows, ny);
+  rc.init(lane - HALO, L, r0, rows, ny);  // the halo lanes start before the stream (clamped to its start)
   unsigned base = 0, dy = 0, dz = 0;  // row offsets (elements; arrays < 2^31 elements)
   T wy = T(1), wz = T(1);             // irregular mesh: widths of the row's cell in y, z
   constexpr unsigned z4 = sizeof(T);
@@ -748,11 +763,12 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
       }
     }
     In in;
-    in.valid = (it << 6) + lane < npos;
+    in.valid = lane >= HALO && it * STEP + lane - HALO < npos;
     // cell index along x (-3 .. nx+2); lanes past the end of the stream sit
-    // on the wave's last row with cp >= L and are clamped into it, so that
-    // every index they map stays in the box (they store nothing)
-    const int cpos = min(rc.cp, L - 1) - 3;
+    // on the wave's last row with cp >= L and are clamped into it, and the
+    // halo lanes of the first iteration onto its start, so that every index
+    // they map stays in the box (they store nothing)
+    const int cpos = min(max(rc.cp, 0), L - 1) - 3;
     in.co = cpos - 3;
     const unsigned ms = (base + (unsigned)map_cell_near(cpos, nx, g.bc[0])) * z4;
 #pragma unroll
@@ -791,13 +807,13 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
       in.b3[1] = T(0.5) * (ld(a.b[1], in.o3) + ld(a.b[1], in.o3 + dy));
       in.b3[2] = T(0.5) * (ld(a.b[2], in.o3) + ld(a.b[2], in.o3 + dz));
     }
-    rc.advance(L, rows, ny);
+    rc.advance(L, rows, ny, STEP);
     return in;
   };
   auto compute = [&](const In& in, const FluidHist<T, HSE>& hi, FluidHist<T, HSE>& ho) {
     T un[5];
     const FluidNU<T> nu = NU ? fluid_nu(in.w, k.dt) : FluidNU<T>{};
-    fluid_position<T, D, GRAV, HSE, LIM, LaneHist, true, NU>(in.u, in.bc, in.phi, in.gh, in.u3, k, nu, hi, ho, un);
+    fluid_position<T, D, GRAV, HSE, LIM, LaneShift, true, NU>(in.u, in.bc, in.phi, in.gh, in.u3, k, nu, hi, ho, un);
     const bool out = in.valid && in.co >= 0 && in.co < nx;
     if (out) {
 #pragma unroll
@@ -1265,16 +1281,18 @@ void field_lanes_kernel(FieldLaunch<T> FL) {
   if (r0 >= nrows) return;  // whole wave exits together
   const int rows = (int)min((long long)a.rows_per_wave, nrows - r0);
   const int npos = rows * L;
-  const int nit = (npos + 63) >> 6;
+  // lanes 0..HALO-1 recompute the last positions of the previous iteration:
+  // the new transverse face of lane i depends on lanes i-8 .. i (the
+  // corrector flux and its neighbour, the limited slopes over three
+  // predictor fluxes, the predictor's upwind fluxes and the smoothed face
+  // velocity each reach back), the edge flux of the normal update on lanes
+  // i-7 .. i, so lanes 8..63 are exact
+  constexpr int HALO = 8, STEP = 64 - HALO;
+  const int nit = (npos + STEP - 1) / STEP;
   const FieldConsts<T> k = field_consts<T, D>(a);
-  RowHist<T> hA[4], hB[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    hA[q].zero();
-    hB[q].zero();
-  }
+  RowHist<T> hA[4], hB[4];  // unused by the carry-free policy
   RowCursor rc;
-  rc.init(lane, L, r0, rows, ry);
+  rc.init(lane - HALO, L, r0, rows, ry);  // the halo lanes start before the stream (clamped to its start)
   RowOffsets ro;
   bool own1 = false, own2 = false;
   FieldRowNU<T> rnr{};  // irregular mesh: the factors of the current row
@@ -1300,8 +1318,8 @@ void field_lanes_kernel(FieldLaunch<T> FL) {
       }
     }
     In in;
-    in.valid = (it << 6) + lane < npos;
-    in.cpos = min(rc.cp, L - 1) - 4;  // cell index along x (-4 .. nx+3), clamped as in the fluid sweep
+    in.valid = lane >= HALO && it * STEP + lane - HALO < npos;
+    in.cpos = min(max(rc.cp, 0), L - 1) - 4;  // cell index along x (-4 .. nx+3), clamped as in the fluid sweep
     in.own1 = own1;
     in.own2 = own2;
     const unsigned mx = (unsigned)map_cell_near(in.cpos, nx, g.bc[0]);
@@ -1327,13 +1345,13 @@ void field_lanes_kernel(FieldLaunch<T> FL) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) in.w[j] = width_at(a.wid[0], in.cpos - 5 + j, nx, g.bc[0]);
     }
-    rc.advance(L, rows, ry);
+    rc.advance(L, rows, ry, STEP);
     return in;
   };
   auto compute = [&](const In& in, const RowHist<T>* hi, RowHist<T>* ho) {
     T bn1, bn2, dbd;
     const FieldPosNU<T> pn = NU ? field_pos_nu(in.w, k.dt) : FieldPosNU<T>{};
-    field_compute<T, LIM, LaneHist, true, NU>(in.f, k, in.rn, pn, hi, ho, bn1, bn2, dbd);
+    field_compute<T, LIM, LaneShift, true, NU>(in.f, k, in.rn, pn, hi, ho, bn1, bn2, dbd);
     const int cb = in.cpos - 4;
     if (in.valid && cb >= 0 && cb < nx) {
       if (in.own1) st(a.bto[0], in.b4off, bn1);
