@@ -17,9 +17,10 @@
 //     Adjacent lanes are adjacent along x, so every access is coalesced.
 //   Lanes (x sweep): the 64 lanes of a wave hold 64 consecutive positions of
 //     a stream of whole x rows (each row padded by its 3-cell halos); the
-//     previous position is the neighbour lane (DPP wave shift), lane 0 taking
-//     lane 63 of the previous iteration.  Again every access is coalesced and
-//     no row is transposed.
+//     previous position is the neighbour lane (DPP wave shift).  The first
+//     lanes of each iteration recompute the positions the previous one ended
+//     on, so no value crosses iterations.  Again every access is coalesced
+//     and no row is transposed.
 #pragma once
 
 #include "layout.h"
@@ -1253,24 +1254,24 @@ __global__ __launch_bounds__(256) void field_strided_kernel(FieldLaunch<T> FL) {
       st(in_sgpr(a.bdo + of), l.fA, ld(in_sgpr(a.bd + of), l.fA) + dbd);
     }
   };
-  // positions s0-4 .. s1+3, padded to an even count (the pad writes nothing).
-  // No lookahead here: the extra registers cost more occupancy than the
-  // prefetch hides (measured).
+  // positions s0-4 .. s1+3, padded to an even count (the pad writes nothing;
+  // the lookahead reads at most two positions past the end, mapped in range).
+  // The lookahead costs one wave per SIMD in FP32 (5 -> 4) and hides more
+  // than that (measured).
   const int npos = (s1 - s0) + 8;
+  FieldIn<T> cur = load(0);
   for (int it = 0; it < npos; it += 2) {
-    compute(it, load(it), hA, hB);
-    compute(it + 1, load(it + 1), hB, hA);
+    const FieldIn<T> nxt = load(it + 1);
+    compute(it, cur, hA, hB);
+    cur = load(it + 2);
+    compute(it + 1, nxt, hB, hA);
   }
 }
 
 // Lanes policy (d = x): waves stream whole rows (y, z) of faces, each padded
 // by 4 positions before and 4 after.
-// In FP32 the kernel needs a few registers more than three waves per SIMD
-// allow; capping it there (one spill and one reload per position) is faster
-// than running two waves (measured).
 template <typename T, int LIM, bool NU>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
-void field_lanes_kernel(FieldLaunch<T> FL) {
+__global__ __launch_bounds__(256) void field_lanes_kernel(FieldLaunch<T> FL) {
   constexpr int D = 0;
   const BoxDesc* d;
   int lw;
