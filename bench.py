@@ -122,20 +122,46 @@ def pct(sorted_vals, q):
     return sorted_vals[k]
 
 
-def cpu_baseline(st, n, cfl, steps, **kw):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_rate(st, n, cfl, steps, threads, **kw):
     from oracle import Oracle
 
-    cores = len(os.sched_getaffinity(0))
-    o = Oracle(*n, cfl=cfl, nthreads=cores, **kw)
+    o = Oracle(*n, cfl=cfl, nthreads=threads, **kw)
     o.set_state(st)
     t0 = time.perf_counter()
     for _ in range(steps):
         o.strang_step(0.0)
     dt = time.perf_counter() - t0
-    ncell = n[0] * n[1] * n[2]
-    return {"value": ncell * steps / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} Strang step(s) of the same {n[0]}x{n[1]}x{n[2]} box from the same initial state, "
-                      f"FP64, {cores} OpenMP threads ({dt:.1f} s)"}
+    o.close()
+    return n[0] * n[1] * n[2] * steps / dt, dt
+
+
+def cpu_baseline(st, n, cfl, steps, per_core_state=None, **kw):
+    """The oracle on the host's cores; with per_core_state = (state, shape,
+    steps), also one thread on that sample for a per-core figure."""
+    cores = len(os.sched_getaffinity(0))
+    rate, dt = _oracle_rate(st, n, cfl, steps, cores, **kw)
+    out = {"value": rate, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+           "sample": f"{steps} Strang step(s) of the same {n[0]}x{n[1]}x{n[2]} box from the same initial state, "
+                     f"FP64, {cores} OpenMP threads ({dt:.1f} s)",
+           "cpu_model": _cpu_model()}
+    if per_core_state is not None:
+        st1, n1, steps1 = per_core_state
+        rate1, dt1 = _oracle_rate(st1, n1, cfl, steps1, 1, **kw)
+        out["per_core"] = {"value": rate1, "unit": "cell-updates/s",
+                           "sample": f"{steps1} Strang step(s) of a {n1[0]}x{n1[1]}x{n1[2]} box, FP64, "
+                                     f"1 thread ({dt1:.1f} s)"}
+    return out
 
 
 def _gen_states(fi, jobs, workers):
@@ -629,7 +655,8 @@ def main():
                        "state_ok": r64["state_ok"]}
     if not args.no_cpu:
         log(f"CPU oracle baseline: {args.cpu_steps} step(s)")
-        out["cpu_baseline"] = cpu_baseline(st, n, cfl, args.cpu_steps, limiter=LIMITERS[args.limiter])
+        out["cpu_baseline"] = cpu_baseline(st, n, cfl, args.cpu_steps, per_core_state=(st, n, 1),
+                                           limiter=LIMITERS[args.limiter])
         log(f"  {out['cpu_baseline']['value']:.3e} cell-updates/s")
     print(json.dumps(out), flush=True)
 
