@@ -122,6 +122,27 @@ def pct(sorted_vals, q):
     return sorted_vals[k]
 
 
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """Device-to-device copy rate in GB/s (bytes read + bytes written): the
+    measured stream peak, reported beside the nominal 8 TB/s."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 / sec / 1e9
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -592,6 +613,8 @@ def main():
     st = fi.random_fourier_state(n, seed=0, mach=1.0, beta=1.0, kmax=16)
     log(f"  {time.perf_counter() - t0:.1f} s")
 
+    copy_gbs = copy_bandwidth(torch)
+    log(f"device copy: {copy_gbs:.0f} GB/s")
     res = {}
     for prec in ("fp32",) + (() if args.no_fp64 else ("fp64",)):
         log(f"GPU {prec}: {args.warmup} warmup + {args.steps} timed steps")
@@ -642,7 +665,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "fluid_sweep_kernel (L_x, L_y, L_z)",
                      "avg_launch_ms": fluid_avg_s * 1e3, "launches": r["fluid_launches"],
-                     "algorithmic_bytes_per_launch": bytes_fluid},
+                     "algorithmic_bytes_per_launch": bytes_fluid,
+                     "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs},
         "state_ok": r["state_ok"],
     }
     if "fp64" in res:
