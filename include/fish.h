@@ -149,8 +149,9 @@ int fish_sweep(fish_ctx* ctx, int op, int dir, double dt);
 /* Diagnostics of the current state, Eq. (18) and Eq. (62), reduced in FP64 in
  * a fixed order: out[0..4] = sums of rho, m_x, m_y, m_z, E times the cell
  * volume; out[5..7] = sums of bx, by, bz over the real faces times the face
- * area; out[8] = max |div b|; out[9] = max |b| over faces.  Synchronises.
- * FISH_ERR_UNSUPPORTED on an irregular mesh (fish_set_spacing). */
+ * area; out[8] = max |div b|; out[9] = max |b| over faces.  On an irregular
+ * mesh (fish_set_spacing) each cell carries its own volume, each face its own
+ * area and each divergence term its cell's width (Sect. 2.5).  Synchronises. */
 int fish_diagnostics(fish_ctx* ctx, double* out10);
 
 /* Irregular Cartesian mesh (Sect. 2.5): the widths of the n cells along axis

@@ -1176,6 +1176,7 @@ int Engine::launch_diag(int slot) {
   DiagArgs<T> a;
   for (int k = 0; k < 5; ++k) a.u[k] = (const T*)pool[cur[k]][k].ptr + b.off;
   for (int k = 0; k < 3; ++k) a.b[k] = (const T*)pool[cur[5 + k]][5 + k].ptr + b.off;
+  for (int k = 0; k < 3; ++k) a.wid[k] = nonuniform ? (const T*)wid[k].ptr : nullptr;
   for (int x = 0; x < 3; ++x) {
     a.g.n[x] = b.n[x];
     a.g.bc[x] = b.bc[x];
@@ -1187,9 +1188,12 @@ int Engine::launch_diag(int slot) {
   const int nblk = (int)std::min<long long>(npartial, std::max<long long>(1, ncell / 4096));
   const long long per_block = (ncell + nblk - 1) / nblk;
   hipLaunchKernelGGL((diag_partial_kernel<T>), dim3(nblk), dim3(kBlock), 0, cfg.stream, a, per_block);
-  const double vol = b.h[0] * b.h[1] * b.h[2];
+  // irregular mesh: every cell and face already carries its own volume or area
+  const double vol = nonuniform ? 1.0 : b.h[0] * b.h[1] * b.h[2];
+  const double ax = nonuniform ? 1.0 : b.h[1] * b.h[2], ay = nonuniform ? 1.0 : b.h[0] * b.h[2],
+               az = nonuniform ? 1.0 : b.h[0] * b.h[1];
   hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(1), 0, cfg.stream, static_cast<const double*>(partial.ptr),
-                     nblk, static_cast<double*>(diag_out.ptr), vol, b.h[1] * b.h[2], b.h[0] * b.h[2], b.h[0] * b.h[1]);
+                     nblk, static_cast<double*>(diag_out.ptr), vol, ax, ay, az);
   return launch_check();
 }
 

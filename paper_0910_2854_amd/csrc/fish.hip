@@ -172,7 +172,6 @@ int fish_advance_to(fish_ctx* c, double t_end, int max_steps, int* steps_taken, 
 int fish_diagnostics(fish_ctx* c, double* out10) {
   if (!c || !out10) return c ? c->e.fail(FISH_ERR_ARG, "null output") : FISH_ERR_ARG;
   if (!c->e.boxes[c->slot].have_state) return c->e.fail(FISH_ERR_ARG, "no state");
-  if (c->e.nonuniform) return c->e.fail(FISH_ERR_UNSUPPORTED, "diagnostics on an irregular mesh");
   return c->e.diagnostics(c->slot, out10);
 }
 

@@ -1685,6 +1685,7 @@ template <typename T>
 struct DiagArgs {
   const T* u[5];
   const T* b[3];
+  const T* wid[3];   // irregular mesh: cell widths per axis (all three set), else null
   Geo g;
   double* partial;   // [nblocks][10]
 };
@@ -1707,36 +1708,45 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(DiagArgs<T> a, long l
     const int j = (int)(r % g.n[1]);
     const int k = (int)(r / g.n[1]);
     const long long s = (long long)i * g.st[0] + (long long)j * g.st[1] + (long long)k * g.st[2];
+    // cell widths; on a uniform mesh the volume and face areas are applied
+    // once at the end, on an irregular one each cell and face carries its own
+    // (Sect. 2.5), and the final factors are 1
+    const bool nu = a.wid[0] != nullptr;
+    const double hx = nu ? (double)a.wid[0][i] : g.h[0];
+    const double hy = nu ? (double)a.wid[1][j] : g.h[1];
+    const double hz = nu ? (double)a.wid[2][k] : g.h[2];
+    const double cw = nu ? hx * hy * hz : 1.0;
+    const double ax = nu ? hy * hz : 1.0, ay = nu ? hx * hz : 1.0, az = nu ? hx * hy : 1.0;
 #pragma unroll
-    for (int f = 0; f < 5; ++f) acc[f] += (double)a.u[f][s];
+    for (int f = 0; f < 5; ++f) acc[f] += (double)a.u[f][s] * cw;
     const long long sx = s + (long long)(map_face(i + 1, g.n[0], g.bc[0]) - i) * g.st[0];
     const long long sy = s + (long long)(map_face(j + 1, g.n[1], g.bc[1]) - j) * g.st[1];
     const long long sz = s + (long long)(map_face(k + 1, g.n[2], g.bc[2]) - k) * g.st[2];
-    // Eq. (62)
-    const double div = ((double)a.b[0][sx] - (double)a.b[0][s]) / g.h[0] +
-                       ((double)a.b[1][sy] - (double)a.b[1][s]) / g.h[1] +
-                       ((double)a.b[2][sz] - (double)a.b[2][s]) / g.h[2];
+    // Eq. (62), each difference over its cell's width
+    const double div = ((double)a.b[0][sx] - (double)a.b[0][s]) / hx +
+                       ((double)a.b[1][sy] - (double)a.b[1][s]) / hy +
+                       ((double)a.b[2][sz] - (double)a.b[2][s]) / hz;
     acc[8] = fmax(acc[8], fabs(div));
     // face sums over real faces: the low face of every cell, plus face n on
     // outflow axes (owned by the last cell)
     const double bx = (double)a.b[0][s], by = (double)a.b[1][s], bz = (double)a.b[2][s];
-    acc[5] += bx;
-    acc[6] += by;
-    acc[7] += bz;
+    acc[5] += bx * ax;
+    acc[6] += by * ay;
+    acc[7] += bz * az;
     acc[9] = fmax(acc[9], fmax(fabs(bx), fmax(fabs(by), fabs(bz))));
     if (g.bc[0] == 1 && i == g.n[0] - 1) {
       const double v = (double)a.b[0][sx];
-      acc[5] += v;
+      acc[5] += v * ax;
       acc[9] = fmax(acc[9], fabs(v));
     }
     if (g.bc[1] == 1 && j == g.n[1] - 1) {
       const double v = (double)a.b[1][sy];
-      acc[6] += v;
+      acc[6] += v * ay;
       acc[9] = fmax(acc[9], fabs(v));
     }
     if (g.bc[2] == 1 && k == g.n[2] - 1) {
       const double v = (double)a.b[2][sz];
-      acc[7] += v;
+      acc[7] += v * az;
       acc[9] = fmax(acc[9], fabs(v));
     }
   }

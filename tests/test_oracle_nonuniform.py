@@ -52,6 +52,36 @@ def test_uniform_state_unchanged_on_a_stretched_mesh():
         np.testing.assert_allclose(out[k], st[k], rtol=1e-13, atol=1e-14)
 
 
+def test_diagnostics_of_a_uniform_state_on_a_stretched_mesh():
+    """Closed form: the totals are the state times the box volume (the product
+    of the width sums), the face sums b times the face areas summed over the
+    real faces (n per periodic axis, n + 1 per outflow axis), and a uniform
+    field has no divergence."""
+    from oracle import OUTFLOW, PERIODIC
+
+    n = (12, 10, 8)
+    ws = [stretched_widths(12, 0.3, 0.0, L=1.3), stretched_widths(10, 0.2, 1.0, L=0.7), stretched_widths(8, 0.25, 2.0)]
+    rho, v, p, bv = 1.3, (0.3, -0.2, 0.1), 0.7, (0.4, 0.2, -0.3)
+    st = fi.uniform_state(n, rho=rho, v=v, p=p, b=bv, gamma=GAMMA)
+    L = [float(np.sum(w)) for w in ws]
+    vol = L[0] * L[1] * L[2]
+    for bc in ((PERIODIC,) * 3, (OUTFLOW, PERIODIC, OUTFLOW)):
+        o = nonuniform_oracle(n, ws, bc=bc)
+        o.set_state(st)
+        d = o.diagnostics()
+        o.close()
+        assert abs(d["mass"] - rho * vol) <= 1e-14 * rho * vol
+        E = st["cell"][4, 0, 0, 0]
+        assert abs(d["energy"] - E * vol) <= 1e-14 * E * vol
+        np.testing.assert_allclose(d["mom"], rho * np.array(v) * vol, rtol=1e-14, atol=1e-15)
+        for a in range(3):
+            nfaces = n[a] + (1 if bc[a] == OUTFLOW else 0)
+            area = vol / L[a]
+            assert abs(d["flux"][a] - bv[a] * nfaces * area) <= 1e-14 * abs(bv[a] * nfaces * area)
+        assert d["divb_max"] <= 1e-13
+        assert d["bmax"] == max(abs(x) for x in bv)
+
+
 def test_conservation_and_divergence_on_a_stretched_mesh():
     n = (14, 12, 10)
     st = fi.random_fourier_state(n, seed=41, mach=0.5, beta=2.0, kmax=2)
