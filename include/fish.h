@@ -164,7 +164,8 @@ int fish_diagnostics(fish_ctx* ctx, double* out10);
  * linearly between the two cell centres, the constraint update (Eq. 64) uses
  * the widths of the face's cell, and the CFL step takes each cell's widths
  * (Eq. 42).  Ghost cells take the width of the cell they map to.  Axes not
- * set keep the uniform width of fish_params.  Synchronises the stream.
+ * set keep the uniform width of fish_params.  The widths reach the device
+ * at the next call that steps, after the stream has drained.
  * FISH_ERR_ARG for a bad axis, a null array or a width that is not finite
  * and positive. */
 int fish_set_spacing(fish_ctx* ctx, int axis, const double* widths);
@@ -289,6 +290,17 @@ int fish_batch_add(fish_batch* b, const fish_box* box, const double* cell5, cons
 
 /* Remove a box and return its pool range.  Synchronises the stream. */
 int fish_batch_remove(fish_batch* b, int id);
+
+/* Irregular Cartesian mesh (Sect. 2.5) of one box of the batch along axis
+ * (0/1/2): the widths of its n cells, as for fish_set_spacing, applied from
+ * the next step on (its CFL speed is taken again).  While any box of the
+ * batch has widths, every box's sweeps take per-cell widths: a uniform box
+ * then runs the irregular formulas with its own spacing, equal to its result
+ * alone to rounding, and a box on an irregular mesh gives bitwise its result
+ * alone.  The widths are copied to the device when the set of boxes changes,
+ * after the stream has drained.  FISH_ERR_ARG for a bad id or axis, a null
+ * array or a width that is not finite and positive. */
+int fish_batch_set_spacing(fish_batch* b, int id, int axis, const double* widths);
 
 /* Download one box's state and time (fish_get_state layouts; NULL skips an
  * array).  FISH_ERR_STATE if the box's sticky state flag is set (a box with a

@@ -99,7 +99,7 @@ EXPORTS = ("fish_create", "fish_destroy", "fish_last_error", "fish_set_state", "
            "fish_batch_use_graph", "fish_batch_autotune", "fish_batch_sync", "fish_batch_timing_enable",
            "fish_batch_timing_read", "fish_set_shape", "fish_batch_set_shape", "fish_server_create", "fish_server_destroy", "fish_server_last_error",
            "fish_server_batch", "fish_server_submit", "fish_server_pump", "fish_server_stats", "fish_set_spacing",
-           "fish_advance_to")
+           "fish_advance_to", "fish_batch_set_spacing")
 KERNEL_FLUID, KERNEL_FIELD, KERNEL_CHECK = 1, 2, 8
 KINDS = ("fluid_x", "fluid_y", "fluid_z", "field_x", "field_y", "field_z", "check")
 
@@ -174,6 +174,8 @@ def load_library(path: str = LIB_PATH):
     lib.fish_set_spacing.argtypes = [vp, ctypes.c_int, P(ctypes.c_double)]
     lib.fish_advance_to.argtypes = [vp, d, ctypes.c_int, P(ctypes.c_int), P(d)]
     lib.fish_set_spacing.restype = ctypes.c_int
+    lib.fish_batch_set_spacing.argtypes = [vp, ctypes.c_int, ctypes.c_int, P(ctypes.c_double)]
+    lib.fish_batch_set_spacing.restype = ctypes.c_int
     lib.fish_batch_set_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int32]
     lib.fish_set_shape.restype = ctypes.c_int
     lib.fish_batch_set_shape.restype = ctypes.c_int
@@ -507,6 +509,14 @@ class Batch:
     def remove(self, box_id):
         self._check(self._lib.fish_batch_remove(self._h, int(box_id)))
         self.shapes.pop(box_id, None)
+
+    def set_spacing(self, box_id, axis, widths):
+        """Irregular mesh (Sect. 2.5) of one box: the widths of its cells along axis."""
+        w = np.ascontiguousarray(widths, dtype=np.float64)
+        if w.shape != (self.shapes[box_id][2 - axis],):
+            raise ValueError("one width per cell along the axis")
+        self._check(self._lib.fish_batch_set_spacing(self._h, int(box_id), int(axis),
+                                                     w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
     def get(self, box_id, check=True):
         nz, ny, nx = self.shapes[box_id]

@@ -37,6 +37,8 @@ struct HostBox {
   long long reserved = 0;   // elements reserved in the pools (aligned)
   bool parked = false;      // kept (state readable) but out of the launches
   hipEvent_t ready = nullptr;  // parked: completes after the last launch that touched the box
+  std::vector<double> widths[3];  // irregular mesh (Sect. 2.5): cell widths per axis, empty = uniform
+  long long woff[3]{};            // offset of the box's widths in the engine's width arrays (table boxes)
 };
 
 struct EngineConfig {
@@ -77,8 +79,10 @@ class Engine {
   long long cap = 0;  // elements per pool
   DeviceBuf pool[2][8];
   DeviceBuf phi;
-  // irregular mesh (Sect. 2.5, one box at slot 0): the widths of its cells per
-  // axis in the storage precision; every sweep then takes per-cell widths
+  // irregular meshes (Sect. 2.5): when a box of the table has cell widths,
+  // the widths of every table box per axis in the storage precision (the
+  // uniform boxes' filled with their spacing), at BoxDesc::woff, and every
+  // sweep takes per-cell widths
   DeviceBuf wid[3];
   bool nonuniform = false;
   int cur[8]{};
@@ -171,7 +175,7 @@ class Engine {
   int autotune(int reps, int* chosen);
   int set_shape(int kind, int value);
   int set_graph(bool on);
-  int set_spacing(int slot, int axis, const double* widths);  // one box: irregular mesh along axis
+  int set_spacing(int slot, int axis, const double* widths);  // irregular mesh along axis
 
  private:
   int ensure_stage(size_t bytes);
@@ -183,7 +187,7 @@ class Engine {
   int last_sweep_and_cfl();
   void invalidate_graph();
   template <typename T>
-  int set_spacing_t(int slot, int axis, const double* widths);
+  int upload_widths(const std::vector<int>& slots, const long long* total);
   void drop_retired_graphs();
   int build_lists();
   template <typename T>

@@ -663,6 +663,16 @@ int Engine::build_lists() {
   const int nb = (int)slots.size();
   std::vector<BoxDesc> desc(nb);
   std::vector<int> list[K_NUM];
+  // irregular meshes: width offsets of every table box when any has widths
+  bool anynu = false;
+  long long wtotal[3] = {0, 0, 0};
+  for (int s : slots)
+    for (int a = 0; a < 3; ++a) anynu = anynu || !boxes[s].widths[a].empty();
+  for (int s : slots)
+    for (int a = 0; a < 3; ++a) {
+      boxes[s].woff[a] = anynu ? wtotal[a] : 0;
+      if (anynu) wtotal[a] += boxes[s].n[a];
+    }
   for (int t = 0; t < nb; ++t) {
     const HostBox& b = boxes[slots[t]];
     BoxDesc& d = desc[t];
@@ -676,6 +686,7 @@ int Engine::build_lists() {
     d.off = b.off;
     d.cfl = b.cfl;
     d.slot = slots[t];
+    for (int a = 0; a < 3; ++a) d.woff[a] = b.woff[a];
     const Tuning defaults = default_tuning();
     for (int k = 0; k < K_NUM; ++k) {
       int par = 1;
@@ -691,6 +702,9 @@ int Engine::build_lists() {
   }
   int rc = set_device();
   if (rc) return rc;
+  if (anynu && (rc = esize == 8 ? upload_widths<double>(slots, wtotal) : upload_widths<float>(slots, wtotal)))
+    return rc;
+  nonuniform = anynu;
   // the spare set is written once every launch that read it has completed
   HIP_TRY(hipEventSynchronize(spare.done));
   drop_retired_graphs();
@@ -896,31 +910,43 @@ int Engine::launch_check_cfl() {
   return launch_check();
 }
 
-// Irregular mesh (Sect. 2.5) of an engine's single box: the widths of its
-// cells along axis, converted to the storage precision.  The other axes keep
-// their uniform width until they are set too.
+// Width arrays of the table's boxes (build_lists): box t's widths along axis
+// a at woff[a]; a box without widths on an axis gets its uniform spacing.
+// Launches still in flight may read the old arrays, so the stream is drained
+// first (only when the set of boxes changes on an irregular mesh).
 template <typename T>
-int Engine::set_spacing_t(int slot, int axis, const double* widths) {
-  const HostBox& b = boxes[slot];
+int Engine::upload_widths(const std::vector<int>& slots, const long long* total) {
+  HIP_TRY(hipStreamSynchronize(cfg.stream));
   for (int a = 0; a < 3; ++a) {
-    if (wid[a].ptr && (a != axis)) continue;
-    const int n = b.n[a];
-    std::vector<T> w(n);
-    for (int i = 0; i < n; ++i) w[i] = (T)(a == axis ? widths[i] : b.h[a]);
-    int rc = 0;
-    if (!wid[a].ptr && (rc = dev_alloc(wid[a], (size_t)n * sizeof(T)))) return rc;
-    HIP_TRY(hipMemcpyAsync(wid[a].ptr, w.data(), (size_t)n * sizeof(T), hipMemcpyHostToDevice, cfg.stream));
+    std::vector<T> w((size_t)total[a]);
+    for (int s : slots) {
+      const HostBox& b = boxes[s];
+      for (int i = 0; i < b.n[a]; ++i)
+        w[(size_t)(b.woff[a] + i)] = (T)(b.widths[a].empty() ? b.h[a] : b.widths[a][i]);
+    }
+    const size_t bytes = w.size() * sizeof(T);
+    if (wid[a].bytes < bytes) {
+      dev_free(wid[a]);
+      int rc = dev_alloc(wid[a], bytes);
+      if (rc) return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(wid[a].ptr, w.data(), bytes, hipMemcpyHostToDevice, cfg.stream));
     HIP_TRY(hipStreamSynchronize(cfg.stream));
   }
-  nonuniform = true;
-  invalidate_graph();
   return 0;
 }
 
+// Irregular mesh (Sect. 2.5) of one box along axis: kept on the host and
+// converted to the storage precision when the table is rebuilt; the other
+// axes keep their uniform width until they are set too.
 int Engine::set_spacing(int slot, int axis, const double* widths) {
   if (slot < 0 || slot >= (int)boxes.size() || !boxes[slot].used) return fail(1, "no box");
-  if (table_slots.size() > 1) return fail(5, "irregular meshes take a single box");
-  return esize == 8 ? set_spacing_t<double>(slot, axis, widths) : set_spacing_t<float>(slot, axis, widths);
+  HostBox& b = boxes[slot];
+  b.widths[axis].assign(widths, widths + b.n[axis]);
+  b.cfl_fresh = false;  // its CFL speed depends on the widths
+  dirty = true;         // the width arrays are rebuilt with the table
+  invalidate_graph();
+  return 0;
 }
 
 // The CFL speed of boxes just added (their step scalars start at zero): the
@@ -1176,7 +1202,7 @@ int Engine::launch_diag(int slot) {
   DiagArgs<T> a;
   for (int k = 0; k < 5; ++k) a.u[k] = (const T*)pool[cur[k]][k].ptr + b.off;
   for (int k = 0; k < 3; ++k) a.b[k] = (const T*)pool[cur[5 + k]][5 + k].ptr + b.off;
-  for (int k = 0; k < 3; ++k) a.wid[k] = nonuniform ? (const T*)wid[k].ptr : nullptr;
+  for (int k = 0; k < 3; ++k) a.wid[k] = nonuniform ? (const T*)wid[k].ptr + b.woff[k] : nullptr;
   for (int x = 0; x < 3; ++x) {
     a.g.n[x] = b.n[x];
     a.g.bc[x] = b.bc[x];
@@ -1200,6 +1226,9 @@ int Engine::launch_diag(int slot) {
 int Engine::diagnostics(int slot, double* out10) {
   int rc = set_device();
   if (rc) return rc;
+  if ((rc = ensure_table())) return rc;  // the width arrays follow the table
+  if (nonuniform && std::find(table_slots.begin(), table_slots.end(), slot) == table_slots.end())
+    return fail(5, "diagnostics of a box outside the launches on an irregular mesh");
   rc = esize == 8 ? launch_diag<double>(slot) : launch_diag<float>(slot);
   if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(out10, diag_out.ptr, 10 * sizeof(double), hipMemcpyDeviceToHost, cfg.stream));

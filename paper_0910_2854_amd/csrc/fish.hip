@@ -362,6 +362,16 @@ int fish_batch_remove(fish_batch* b, int id) {
   return b->e.remove_box(id);
 }
 
+int fish_batch_set_spacing(fish_batch* b, int id, int axis, const double* widths) {
+  if (!b) return FISH_ERR_ARG;
+  if (id < 0 || id >= (int)b->e.boxes.size() || !b->e.boxes[id].used) return b->e.fail(FISH_ERR_ARG, "no such box");
+  if (axis < 0 || axis > 2 || !widths) return b->e.fail(FISH_ERR_ARG, "bad axis or widths");
+  const int n = b->e.boxes[id].n[axis];
+  for (int i = 0; i < n; ++i)
+    if (!(widths[i] > 0.0) || !std::isfinite(widths[i])) return b->e.fail(FISH_ERR_ARG, "widths must be finite and > 0");
+  return b->e.set_spacing(id, axis, widths);
+}
+
 int fish_batch_get(fish_batch* b, int id, double* cell5, double* bx, double* by, double* bz, double* t_out) {
   if (!b) return FISH_ERR_ARG;
   if (id < 0 || id >= (int)b->e.boxes.size() || !b->e.boxes[id].used) return b->e.fail(FISH_ERR_ARG, "no such box");

@@ -38,6 +38,7 @@ struct BoxDesc {
   int wave0[K_NUM];   // first wave of the box in each kind's list
   int par[K_NUM];     // rows per wave (x kinds), segment length (y/z kinds), cells per lane (check)
   int pad;
+  long long woff[3];  // irregular meshes: element offset of the box's cell widths in each axis's width array
 };
 
 struct WorkList {

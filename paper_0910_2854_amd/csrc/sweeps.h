@@ -260,7 +260,7 @@ struct FluidLaunch {
   T* uo[5];
   const T* b[3];
   const T* phi;
-  const T* wid[3];  // irregular mesh (one box): widths of the cells per axis
+  const T* wid[3];  // irregular meshes: every table box's cell widths per axis (at BoxDesc::woff), else null
   double gamma, alpha;
   WorkList wl;
   Scalars* sc;
@@ -281,7 +281,7 @@ __device__ __forceinline__ FluidArgs<T> fluid_view(const FluidLaunch<T>& L, cons
   for (int i = 0; i < 3; ++i) a.b[i] = L.b[i] + off;
   a.phi = L.phi ? L.phi + off : nullptr;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) a.wid[i] = L.wid[i];
+  for (int i = 0; i < 3; ++i) a.wid[i] = L.wid[i] ? L.wid[i] + d.woff[i] : nullptr;
   a.g = d.g;
   a.gamma = L.gamma;
   a.alpha = L.alpha;
@@ -883,7 +883,7 @@ struct FieldLaunch {
   const T* bd;
   T* bto[2];
   T* bdo;
-  const T* wid[3];  // irregular mesh (one box): widths of the cells per axis
+  const T* wid[3];  // irregular meshes: every table box's cell widths per axis (at BoxDesc::woff), else null
   WorkList wl;
   Scalars* sc;
 };
@@ -901,7 +901,7 @@ __device__ __forceinline__ FieldArgs<T> field_view(const FieldLaunch<T>& L, cons
   a.bto[1] = L.bto[1] + off;
   a.bdo = L.bdo + off;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) a.wid[i] = L.wid[i];
+  for (int i = 0; i < 3; ++i) a.wid[i] = L.wid[i] ? L.wid[i] + d.woff[i] : nullptr;
   a.g = d.g;
   const int D = KIND - K_FIELD_X;
   a.seg = d.par[KIND];
@@ -1555,7 +1555,7 @@ template <typename T>
 struct CheckLaunch {
   const T* u[5];
   const T* b[3];
-  const T* wid[3];  // irregular mesh (one box), else null
+  const T* wid[3];  // irregular meshes: every table box's cell widths per axis (at BoxDesc::woff), else null
   double gamma;
   WorkList wl;
   Scalars* sc;
@@ -1593,6 +1593,9 @@ __global__ __launch_bounds__(256) void check_cfl_kernel(CheckLaunch<T> L) {
   double smax[3] = {0.0, 0.0, 0.0};
   double cnu = 0.0;                      // irregular mesh: per-cell speeds over widths
   const bool nu = L.wid[0] != nullptr;   // uniform across the launch
+  const T* wx = nu ? L.wid[0] + d->woff[0] : nullptr;
+  const T* wy = nu ? L.wid[1] + d->woff[1] : nullptr;
+  const T* wz = nu ? L.wid[2] + d->woff[2] : nullptr;
   int bad = 0;
   for (; c < c1; c += 64) {
     const unsigned s = (unsigned)x + (unsigned)y * st1 + (unsigned)zz * st2;
@@ -1610,7 +1613,7 @@ __global__ __launch_bounds__(256) void check_cfl_kernel(CheckLaunch<T> L) {
     double sp[3];
     cell_cfl_speeds<T>(uc, bc, L.gamma, g, sp, bad);
     if (nu) {
-      cnu = fmax(cnu, cfl_of_cell(sp, (double)L.wid[0][x], (double)L.wid[1][y], (double)L.wid[2][zz], g));
+      cnu = fmax(cnu, cfl_of_cell(sp, (double)wx[x], (double)wy[y], (double)wz[zz], g));
     } else {
 #pragma unroll
       for (int dd = 0; dd < 3; ++dd) smax[dd] = fmax(smax[dd], sp[dd]);

@@ -177,3 +177,85 @@ def test_nonuniform_diagnostics_match_oracle(case, prec, tol):
             g.strang_step(dt)
     o.close()
     g.close()
+
+
+def _mild(n, seed):
+    # every box stays valid for 8 steps on the oracle, on its mesh
+    return fi.random_fourier_state(n, seed=seed, mach=0.4, beta=4.0, kmax=2)
+
+
+def _alone(n, bc, seed, prec, steps, nu):
+    import paper_0910_2854_amd as fish
+    g = fish.Box(*n, precision=prec, bc=bc)
+    if nu:
+        for a, w in enumerate(widths_for(n)):
+            g.set_spacing(a, w)
+    g.set_state(_mild(n, seed))
+    for _ in range(steps):
+        g.strang_step(0.0)
+    out = g.get_state()
+    g.close()
+    return out
+
+
+def _close_to(got, ref, prec, n):
+    if prec == "fp64":
+        assert max_rel(got, ref) <= 1e-12, n
+        assert abs(got["t"] - ref["t"]) <= 1e-13 * ref["t"]
+    else:
+        assert max(per_field_rel_l1(got, ref).values()) <= 1e-5, n
+        assert abs(got["t"] - ref["t"]) <= 1e-6 * ref["t"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_with_irregular_and_uniform_boxes(prec):
+    """A batch mixing boxes on stretched meshes with uniform ones, stepped
+    with per-box CFL steps: an irregular box gives bitwise its result alone;
+    a uniform box runs the irregular formulas with its own spacing, equal to
+    its uniform result alone to rounding; the irregular boxes match the
+    oracle (FP64).  Once the irregular boxes leave, the uniform kernels take
+    over again."""
+    import paper_0910_2854_amd as fish
+    boxes = [((20, 14, 10), (PERIODIC,) * 3, 21, True), ((16, 12, 10), (PERIODIC,) * 3, 22, False),
+             ((11, 9, 13), (OUTFLOW,) * 3, 23, True), ((150, 5, 4), (PERIODIC, OUTFLOW, PERIODIC), 24, False)]
+    steps = 3
+    print(f"batch of irregular and uniform boxes, {prec}", flush=True)
+    b = fish.Batch(256 << 20, max_boxes=16, precision=prec)
+    ids = []
+    for n, bc, seed, nu in boxes:
+        i = b.add(_mild(n, seed), bc=bc)
+        if nu:
+            for a, w in enumerate(widths_for(n)):
+                b.set_spacing(i, a, w)
+        ids.append(i)
+    b.step(steps)
+    for (n, bc, seed, nu), i in zip(boxes, ids):
+        print(f"  box {n} irregular={nu}", flush=True)
+        got = b.get(i)
+        ref = _alone(n, bc, seed, prec, steps, nu)
+        if not nu:
+            _close_to(got, ref, prec, n)
+            continue
+        for k in ("cell", "bx", "by", "bz"):
+            assert np.array_equal(got[k], ref[k]), (n, k)
+        assert got["t"] == ref["t"]
+        if prec == "fp64":
+            o = Oracle(*n, bc=bc)
+            for a, w in enumerate(widths_for(n)):
+                o.set_spacing(a, w)
+            o.set_state(_mild(n, seed))
+            for _ in range(steps):
+                o.strang_step(0.0)
+            so = o.get_state()
+            o.close()
+            assert max(per_field_rel_l1(got, so).values()) <= 1e-10
+            assert abs(got["t"] - so["t"]) <= 1e-12 * so["t"]
+    for (n, bc, seed, nu), i in zip(boxes, ids):
+        if nu:
+            b.remove(i)
+    b.step(1)
+    for (n, bc, seed, nu), i in zip(boxes, ids):
+        if not nu:
+            print(f"  box {n} after the irregular boxes left", flush=True)
+            _close_to(b.get(i), _alone(n, bc, seed, prec, steps + 1, False), prec, n)
+    b.close()
