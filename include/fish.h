@@ -358,6 +358,10 @@ typedef struct fish_request {
   double *out_cell5, *out_bx, *out_by, *out_bz;  /* final state, written at
                                         retirement (any may be NULL)             */
   int64_t tag;                       /* returned by fish_server_pump on completion  */
+  const double* widths[3];           /* irregular mesh (Sect. 2.5): the cell widths
+                                        along each axis (n values, finite and > 0,
+                                        as for fish_set_spacing), or NULL for the
+                                        uniform spacing of box; read at admission */
 } fish_request;
 
 /* Create a server whose batch has the given parameters; chunk_steps >= 1 is

@@ -87,6 +87,7 @@ class Request(ctypes.Structure):
         ("out_cell5", ctypes.POINTER(ctypes.c_double)), ("out_bx", ctypes.POINTER(ctypes.c_double)),
         ("out_by", ctypes.POINTER(ctypes.c_double)), ("out_bz", ctypes.POINTER(ctypes.c_double)),
         ("tag", ctypes.c_int64),
+        ("widths", ctypes.POINTER(ctypes.c_double) * 3),
     ]
 
 
@@ -584,7 +585,7 @@ class Server:
         if rc != FISH_OK:
             raise FishError(rc, "fish_server_create failed: " + lib.fish_last_error(None).decode())
         self._h = h
-        self._live = {}   # tag -> (request, input arrays, output dict) kept alive until completion
+        self._live = {}   # tag -> (request, input arrays, phi, output dict, widths) kept alive until completion
         self._done = (ctypes.c_int64 * 4096)()
         self._status = (ctypes.c_int32 * 4096)()
 
@@ -603,7 +604,9 @@ class Server:
         except Exception:
             pass
 
-    def submit(self, tag, st, nsteps, h=None, cfl=0.5, bc=(PERIODIC,) * 3):
+    def submit(self, tag, st, nsteps, h=None, cfl=0.5, bc=(PERIODIC,) * 3, widths=None):
+        """Queue a request; widths: None, or per axis None or the cell widths
+        of an irregular mesh (Sect. 2.5)."""
         cell = np.ascontiguousarray(st["cell"], dtype=np.float64)
         _, nz, ny, nx = cell.shape
         arrs = [cell] + [np.ascontiguousarray(st[k], dtype=np.float64) for k in ("bx", "by", "bz")]
@@ -617,8 +620,15 @@ class Server:
         r.phi = _dptr(phi)
         r.out_cell5, r.out_bx, r.out_by, r.out_bz = (_dptr(out[k]) for k in ("cell", "bx", "by", "bz"))
         r.tag = int(tag)
+        ws = [None, None, None]
+        for a in range(3):
+            if widths is not None and widths[a] is not None:
+                ws[a] = np.ascontiguousarray(widths[a], dtype=np.float64)
+                if ws[a].shape != ((nx, ny, nz)[a],):
+                    raise ValueError("one width per cell along the axis")
+            r.widths[a] = _dptr(ws[a])
         self._check(self._lib.fish_server_submit(self._h, ctypes.byref(r)))
-        self._live[int(tag)] = (r, arrs, phi, out)
+        self._live[int(tag)] = (r, arrs, phi, out, ws)
 
     def pump(self):
         """One scheduling round; returns [(tag, status, output state)] of the
@@ -628,7 +638,7 @@ class Server:
         res = []
         for i in range(n.value):
             tag = int(self._done[i])
-            _, _, _, out = self._live.pop(tag)
+            out = self._live.pop(tag)[3]
             res.append((tag, int(self._status[i]), out))
         return res
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <deque>
 #include <new>
 #include <string>
@@ -83,6 +84,12 @@ int fish_server_submit(fish_server* s, const fish_request* r) {
   const double h[3] = {r->box.dx, r->box.dy, r->box.dz};
   const int bc[3] = {r->box.bc[0], r->box.bc[1], r->box.bc[2]};
   if (Engine::validate_box(n, h, bc, r->box.cfl)) return sfail(s, FISH_ERR_ARG, "invalid box geometry");
+  for (int a = 0; a < 3; ++a) {
+    if (!r->widths[a]) continue;
+    for (int i = 0; i < n[a]; ++i)
+      if (!(r->widths[a][i] > 0.0) || !std::isfinite(r->widths[a][i]))
+        return sfail(s, FISH_ERR_ARG, "widths must be finite and > 0");
+  }
   if (fish_box_pool_bytes(&r->box, s->precision, s->gravity) > s->pool_bytes)
     return sfail(s, FISH_ERR_NOMEM, "request larger than the whole pool");
   s->queue.push_back(*r);
@@ -150,6 +157,8 @@ int fish_server_pump(fish_server* s, int64_t* done_tags, int32_t* done_status, i
     if (rc == FISH_ERR_NOMEM) break;  // wait for a retirement
     if (rc) return sfail(s, rc, e.err);
     if ((rc = e.upload(id, r.cell5, r.bx, r.by, r.bz, r.phi))) return sfail(s, rc, e.err);
+    for (int a = 0; a < 3; ++a)
+      if (r.widths[a] && (rc = e.set_spacing(id, a, r.widths[a]))) return sfail(s, rc, e.err);
     s->resident.push_back({r, id, r.nsteps});
     s->queue.pop_front();
     added = true;

@@ -259,3 +259,34 @@ def test_batch_with_irregular_and_uniform_boxes(prec):
             print(f"  box {n} after the irregular boxes left", flush=True)
             _close_to(b.get(i), _alone(n, bc, seed, prec, steps + 1, False), prec, n)
     b.close()
+
+
+def test_server_serves_requests_on_irregular_meshes():
+    """Requests that carry cell widths beside uniform ones (FP64): an
+    irregular request's result is bitwise its box stepped alone, a uniform
+    one's equal to its result alone to rounding."""
+    import paper_0910_2854_amd as fish
+    reqs = [((20, 14, 10), (PERIODIC,) * 3, 4, 31, True), ((16, 12, 10), (PERIODIC,) * 3, 3, 32, False),
+            ((11, 9, 13), (OUTFLOW,) * 3, 5, 33, True), ((12, 10, 8), (PERIODIC,) * 3, 2, 34, False)]
+    print(f"server with {len(reqs)} requests, irregular and uniform", flush=True)
+    srv = fish.Server(512 << 20, chunk_steps=2, precision="fp64")
+    for tag, (n, bc, k, seed, nu) in enumerate(reqs):
+        srv.submit(tag, _mild(n, seed), k, bc=bc, widths=widths_for(n) if nu else None)
+    done = {}
+    for _ in range(100):
+        for tag, status, out in srv.pump():
+            assert status == fish.FISH_OK, tag
+            done[tag] = out
+        if len(done) == len(reqs):
+            break
+    assert len(done) == len(reqs)
+    for tag, (n, bc, k, seed, nu) in enumerate(reqs):
+        ref = _alone(n, bc, seed, "fp64", k, nu)
+        if nu:
+            for f in ("cell", "bx", "by", "bz"):
+                assert np.array_equal(done[tag][f], ref[f]), (n, f)
+        else:
+            assert max_rel(done[tag], ref) <= 1e-12, n
+    with pytest.raises(fish.FishError):
+        srv.submit(99, _mild((8, 8, 8), 1), 1, widths=[np.full(8, -1.0), None, None])
+    srv.close()
