@@ -222,8 +222,9 @@ int fish_set_shape(fish_ctx* ctx, int kind, int32_t value);
 /* Self-test of the wavefront lane-shift primitive the x sweeps stream with
  * (no context): one wave of 64 lanes runs two iterations with lane values
  * v = 100*it + lane; out128[64*it + lane] receives the value one stream
- * position back (lane-1 of the same iteration, lane 63 of the previous one
- * for lane 0; -1 before the first).  Synchronous; the caller owns out128. */
+ * position back, i.e. lane - 1's of the same iteration, and 0 in lane 0 (the
+ * x sweeps make their first lanes a halo, so nothing crosses iterations).
+ * Synchronous; the caller owns out128. */
 int fish_selftest_lane_shift(int device, float* out128);
 
 /* ------------------------------------------------------------------------

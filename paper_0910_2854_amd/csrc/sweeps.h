@@ -106,31 +106,6 @@ struct StridedHist {
   }
 };
 
-// Lane shift with a carry across iterations (the two-positions-per-lane B_x
-// kernel, which keeps its history from one iteration to the next).
-__device__ __forceinline__ int lane_prev_bits(int cur, int& carry) {
-  // wave_shr:1 -- lane i takes lane i-1; lane 0 keeps `old` = carry (whose
-  // lane 0 holds lane 63 of the previous iteration); then carry = wave_ror:1.
-  const int o = __builtin_amdgcn_update_dpp(carry, cur, 0x138, 0xf, 0xf, false);
-  carry = __builtin_amdgcn_mov_dpp(cur, 0x13C, 0xf, 0xf, false);
-  return o;
-}
-__device__ __forceinline__ float lane_prev(float cur, float& carry) {
-  int c = __float_as_int(carry);
-  const int o = lane_prev_bits(__float_as_int(cur), c);
-  carry = __int_as_float(c);
-  return __int_as_float(o);
-}
-__device__ __forceinline__ double lane_prev(double cur, double& carry) {
-  const long long cb = __double_as_longlong(cur);
-  long long kb = __double_as_longlong(carry);
-  int klo = (int)(kb & 0xffffffffll), khi = (int)(kb >> 32);
-  const int olo = lane_prev_bits((int)(cb & 0xffffffffll), klo);
-  const int ohi = lane_prev_bits((int)(cb >> 32), khi);
-  carry = __longlong_as_double(((long long)khi << 32) | (unsigned int)klo);
-  return __longlong_as_double(((long long)ohi << 32) | (unsigned int)olo);
-}
-
 // Lanes policy without a carry: lane i takes lane i-1 by one DPP shift and
 // lane 0 takes zero.  The caller makes the wave's first lanes a halo that
 // recomputes the positions the previous iteration ended on, so nothing has
@@ -1383,45 +1358,47 @@ __global__ __launch_bounds__(256) void field_lanes_kernel(FieldLaunch<T> FL) {
 // The x field sweep with lane l holding stream positions 2l and 2l+1 of a
 // 128-position window.  The pipeline runs stage by stage over both: the
 // value one position back is the lane's own register for 2l+1 and the
-// neighbour lane's (one DPP shift, lane 0 taking lane 63 of the previous
-// window) for 2l, so each history value costs one shift per two cells.
+// neighbour lane's (one DPP shift) for 2l, so each history value costs one
+// shift per two cells.  As in the one-position kernel, the first lanes of a
+// window recompute the positions the previous one ended on (8 positions, 4
+// lanes), so nothing crosses windows.
 template <typename T>
-__device__ __forceinline__ void prev2(const T (&x)[2], T (&p)[2], T& carry) {
+__device__ __forceinline__ void prev2(const T (&x)[2], T (&p)[2]) {
   p[1] = x[0];
-  p[0] = lane_prev(x[1], carry);
+  p[0] = lane_shr(x[1]);
 }
 
-// row_position for both positions of the lane; h holds the carries.
+// row_position for both positions of the lane.
 template <typename T, int LIM, bool NEED_BN>
 __device__ __forceinline__ void row_position2(const T (&w0)[2], const T (&bb)[2], const T (&b4)[2], T k_half,
-                                              T k_full, RowHist<T>& h, T (&bn)[2], T (&P2c)[2]) {
+                                              T k_full, T (&bn)[2], T (&P2c)[2]) {
   T w1[2], w2[2], vbc[2], b1[2], fc[2], vb1[2], V[2], f2[2], P1[2], p1[2], b2[2], bp[2], fp2[2];
   T vb2[2], vb3[2], fp3[2], fp4[2], fp5[2];
-  prev2(w0, w1, h.w1);
-  prev2(w1, w2, h.w2);
+  prev2(w0, w1);
+  prev2(w1, w2);
 #pragma unroll
   for (int j = 0; j < 2; ++j) vbc[j] = T(0.25) * ((w2[j] + w0[j]) + T(2) * w1[j]);  // v-bar of c-1 (as above)
-  prev2(bb, b1, h.b1);
+  prev2(bb, b1);
 #pragma unroll
   for (int j = 0; j < 2; ++j) fc[j] = vbc[j] * b1[j];
-  prev2(vbc, vb1, h.vb1);
+  prev2(vbc, vb1);
 #pragma unroll
   for (int j = 0; j < 2; ++j) V[j] = T(0.5) * (vb1[j] + vbc[j]);
-  prev2(fc, f2, h.f2);
+  prev2(fc, f2);
 #pragma unroll
   for (int j = 0; j < 2; ++j) P1[j] = V[j] > T(0) ? f2[j] : fc[j];
-  prev2(P1, p1, h.p1);
-  prev2(b1, b2, h.b2);
+  prev2(P1, p1);
+  prev2(b1, b2);
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     bp[j] = b2[j] - k_half * (P1[j] - p1[j]);
     fp2[j] = vb1[j] * bp[j];
   }
-  prev2(vb1, vb2, h.vb2);
-  prev2(vb2, vb3, h.vb3);
-  prev2(fp2, fp3, h.fp3);
-  prev2(fp3, fp4, h.fp4);
-  prev2(fp4, fp5, h.fp5);
+  prev2(vb1, vb2);
+  prev2(vb2, vb3);
+  prev2(fp2, fp3);
+  prev2(fp3, fp4);
+  prev2(fp4, fp5);
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const T V7 = T(0.5) * (vb3[j] + vb2[j]);
@@ -1431,7 +1408,7 @@ __device__ __forceinline__ void row_position2(const T (&w0)[2], const T (&bb)[2]
   }
   if (NEED_BN) {
     T P2[2];
-    prev2(P2c, P2, h.P2);
+    prev2(P2c, P2);
 #pragma unroll
     for (int j = 0; j < 2; ++j) bn[j] = b4[j] - k_full * (P2c[j] - P2[j]);
   }
@@ -1456,16 +1433,14 @@ __global__ __launch_bounds__(256) void field_lanes2_kernel(FieldLaunch<T> FL) {
   if (r0 >= nrows) return;  // whole wave exits together
   const int rows = (int)min((long long)a.rows_per_wave, nrows - r0);
   const int npos = rows * L;
-  const int nit = (npos + 127) >> 7;
+  constexpr int HALO = 8, STEP = 128 - HALO;  // positions
+  const int nit = (npos + STEP - 1) / STEP;
   const FieldConsts<T> k = field_consts<T, D>(a);
-  RowHist<T> h[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) h[q].zero();
   RowCursor rc[2];
   RowOffsets ro[2];
   bool own1[2] = {false, false}, own2[2] = {false, false};
 #pragma unroll
-  for (int j = 0; j < 2; ++j) rc[j].init(2 * lane + j, L, r0, rows, ry);
+  for (int j = 0; j < 2; ++j) rc[j].init(2 * lane + j - HALO, L, r0, rows, ry);
   constexpr unsigned z = sizeof(T);
   struct In {
     FieldIn<T> f;
@@ -1480,8 +1455,8 @@ __global__ __launch_bounds__(256) void field_lanes2_kernel(FieldLaunch<T> FL) {
       own2[j] = rc[j].y < g.n[1];
     }
     In in;
-    in.valid = (it << 7) + 2 * lane + j < npos;
-    in.cpos = min(rc[j].cp, L - 1) - 4;  // clamped as in the fluid sweep
+    in.valid = 2 * lane + j >= HALO && it * STEP + 2 * lane + j - HALO < npos;
+    in.cpos = min(max(rc[j].cp, 0), L - 1) - 4;  // clamped as in the fluid sweep
     in.own1 = own1[j];
     in.own2 = own2[j];
     const unsigned mx = (unsigned)map_cell_near(in.cpos, nx, g.bc[0]);
@@ -1502,7 +1477,7 @@ __global__ __launch_bounds__(256) void field_lanes2_kernel(FieldLaunch<T> FL) {
     in.f.b4a = ld(a.bt[0], in.b4off);
     in.f.b4c = ld(a.bt[1], in.b4off);
     in.fo = (ro[j].base + (unsigned)max(in.cpos - 3, 0)) * z;
-    rc[j].advance(L, rows, ry, 128);
+    rc[j].advance(L, rows, ry, STEP);
     return in;
   };
   auto compute = [&](const In (&in)[2]) {
@@ -1524,10 +1499,10 @@ __global__ __launch_bounds__(256) void field_lanes2_kernel(FieldLaunch<T> FL) {
       b4c[j] = in[j].f.b4c;
     }
     T bn1[2], bn2[2], eA[2], eB[2], eC[2], eD[2], dummy[2];
-    row_position2<T, LIM, true>(wA, bA, b4a, k.k_half, k.k_full, h[0], bn1, eA);
-    row_position2<T, LIM, false>(wB, bB, b4a, k.k_half, k.k_full, h[1], dummy, eB);
-    row_position2<T, LIM, true>(wC, bC, b4c, k.k_half, k.k_full, h[2], bn2, eC);
-    row_position2<T, LIM, false>(wD, bD, b4c, k.k_half, k.k_full, h[3], dummy, eD);
+    row_position2<T, LIM, true>(wA, bA, b4a, k.k_half, k.k_full, bn1, eA);
+    row_position2<T, LIM, false>(wB, bB, b4a, k.k_half, k.k_full, dummy, eB);
+    row_position2<T, LIM, true>(wC, bC, b4c, k.k_half, k.k_full, bn2, eC);
+    row_position2<T, LIM, false>(wD, bD, b4c, k.k_half, k.k_full, dummy, eD);
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       // Eq. (64), physical signs
@@ -1792,14 +1767,13 @@ __global__ void diag_final_kernel(const double* partial, int nblocks, double* ou
   out[9] = acc[9];
 }
 
-// Self-test of the lane-shift primitive: out[64*it + lane] = previous
-// position's value of (100*it + lane) over two iterations (128 entries).
+// Self-test of the lane-shift primitive: out[64*it + lane] = the value of
+// lane - 1 of (100*it + lane), 0 in lane 0, over two iterations (128 entries).
 __global__ void lane_shift_selftest_kernel(float* out) {
   const int lane = threadIdx.x & 63;
-  float carry = -1.0f;
   for (int it = 0; it < 2; ++it) {
     const float cur = (float)(100 * it + lane);
-    out[64 * it + lane] = lane_prev(cur, carry);
+    out[64 * it + lane] = lane_shr(cur);
   }
 }
 

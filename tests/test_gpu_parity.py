@@ -76,14 +76,14 @@ def _state(n, bc, gravity, seed):
 
 def test_lane_shift_primitive():
     """The x sweeps stream through the wavefront with a one-lane shift; check
-    its lane layout directly (lane 0 takes lane 63 of the previous iteration)."""
+    its lane layout directly (lane i takes lane i - 1, lane 0 takes 0)."""
     import paper_0910_2854_amd as fish
     print("lane-shift self-test", flush=True)
     out = fish.selftest_lane_shift(0)
     expect = np.empty(128, dtype=np.float32)
     for it in range(2):
         for lane in range(64):
-            expect[64 * it + lane] = (100 * it + lane - 1) if lane > 0 else (-1 if it == 0 else 63)
+            expect[64 * it + lane] = (100 * it + lane - 1) if lane > 0 else 0
     np.testing.assert_array_equal(out, expect)
 
 
