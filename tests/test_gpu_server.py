@@ -97,3 +97,51 @@ def test_server_completes_a_bad_request_with_its_status():
             break
     assert got == {7: fish.FISH_ERR_STATE, 8: fish.FISH_OK}
     srv.close()
+
+
+@pytest.mark.timeout(600)
+def test_server_full_size_requests_equal_alone():
+    """The serving workload the benchmark times, at full size: 12 requests of
+    its saturated mix (edges 32-192, 10-200 double steps, Mach 0.5, beta 10),
+    all queued at once into a server with the benchmark's settings (FP32,
+    graph replays, chunks of 5 steps); every completed request's state is
+    bitwise its box stepped alone the same number of steps."""
+    import paper_0910_2854_amd as fish
+    reqs = fi.serving_requests(12, rate=1.0, seed=7)
+
+    def state(r):
+        e = r["edge"]
+        return fi.random_fourier_state((e, e, e), seed=r["seed"], mach=0.5, beta=10.0, kmax=4)
+
+    print(f"server full size: edges {[r['edge'] for r in reqs]}, steps {[r['steps'] for r in reqs]}", flush=True)
+    states = [state(r) for r in reqs]
+    pool = sum(fish.box_pool_bytes((r["edge"],) * 3, "fp32") for r in reqs) + (64 << 20)
+    srv = fish.Server(pool, chunk_steps=5, max_boxes=4096, precision="fp32")
+    srv.use_graph(True)
+    for tag, r in enumerate(reqs):
+        srv.submit(tag, states[tag], r["steps"])
+    done = {}
+    for _ in range(1000):
+        for tag, status, out in srv.pump():
+            done[tag] = (status, out)
+        if len(done) == len(reqs):
+            break
+    srv.close()
+    assert len(done) == len(reqs)
+    for tag, r in enumerate(reqs):
+        e = r["edge"]
+        print(f"  request {tag}: edge {e}, {r['steps']} steps", flush=True)
+        g = fish.Box(e, e, e, precision="fp32")
+        g.set_state(states[tag])
+        for _ in range(r["steps"]):
+            g.strang_step(0.0)
+        status, out = done[tag]
+        if status != fish.FISH_OK:
+            with pytest.raises(fish.FishError):
+                g.get_state()
+            g.close()
+            continue
+        ref = g.get_state()
+        g.close()
+        for k in FIELDS:
+            assert np.array_equal(out[k], ref[k]), (tag, k)
