@@ -31,6 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles
+# at 2.4 GHz, i.e. 3.93e13 lane-instructions/s (no packed FP32 here)
+VALU_PEAK_LANE_INSTS = 256 * 4 * 64 / 4 * 2.4e9
 LIMITERS = {"minmod": 0, "vanleer": 1, "switch": 2}
 METRIC = "cell-updates/s per Strang step (FP32 vs FP64) + % HBM roofline; p50/p99 latency"
 
@@ -47,20 +50,21 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(name, esize, cells):
-    """HBM bytes per launch of the fluid sweep from the committed counter run,
-    or None if the kernel source changed since the counters were taken."""
+def load_counters(name, esize, cells):
+    """(HBM bytes, VALU wave instructions) per launch of the fluid sweep from
+    the committed counter runs, or (None, None) if the kernel source changed
+    since the counters were taken."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
-        return None
+        return None, None
     try:
         with open(path) as f:
             rec = json.load(f)
     except Exception:
-        return None
+        return None, None
     if rec.get("kernel_hash") != kernel_source_hash() or rec.get("cells") != cells or rec.get("esize") != esize:
-        return None
-    return rec.get("bytes_per_launch")
+        return None, None
+    return rec.get("bytes_per_launch"), rec.get("valu_wave_insts_per_launch")
 
 
 def stretched_widths(n, amp, phase):
@@ -632,7 +636,17 @@ def main():
     achieved = bytes_fluid / fluid_avg_s / 1e9
     # the counters were taken on the default configuration's kernels only
     default_kernels = args.limiter == "vanleer" and not args.stretch
-    traffic = load_traffic("fluid_sweep_traffic_256.json", esize, ncell) if default_kernels else None
+    traffic, valu_insts = (load_counters("fluid_sweep_traffic_256.json", esize, ncell) if default_kernels
+                           else (None, None))
+    # the same launches against the VALU issue peak: the step is bound by
+    # instruction issue, not by HBM (the counters' instructions over the live
+    # launch time)
+    alu = None
+    if valu_insts:
+        lane_insts = valu_insts * 64 / fluid_avg_s
+        alu = {"achieved": lane_insts / 1e12, "peak": VALU_PEAK_LANE_INSTS / 1e12,
+               "unit": "T VALU lane-instructions/s", "frac": lane_insts / VALU_PEAK_LANE_INSTS,
+               "valu_per_cell": valu_insts * 64 / ncell}
     out = {
         "metric": METRIC,
         "value": value,
@@ -666,7 +680,8 @@ def main():
                      "kernel": "fluid_sweep_kernel (L_x, L_y, L_z)",
                      "avg_launch_ms": fluid_avg_s * 1e3, "launches": r["fluid_launches"],
                      "algorithmic_bytes_per_launch": bytes_fluid,
-                     "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs},
+                     "measured_copy_GBs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs,
+                     "valu_issue": alu},
         "state_ok": r["state_ok"],
     }
     if "fp64" in res:
