@@ -1252,7 +1252,7 @@ int Engine::autotune(int reps, int* chosen) {
   hipLaunchKernelGGL(finalize_dt_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream, (const BoxDesc*)table.ptr,
                      nb, (Scalars*)scal.ptr);
   if ((rc = launch_check())) return rc;
-  static const int lanes_c[] = {256, 384, 512, 768, 1024, 1536, 2048, 3072};
+  static const int lanes_c[] = {256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144};
   static const int seg_c[] = {8, 16, 24, 32, 48, 64, 96, 128, 192, 256};
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
