@@ -24,7 +24,9 @@ the field advection; the closed forms of the fast speed; the HSE reductions;
 split gravity (closed-form kick, hydrostatic atmosphere at second order); the
 Mach limiter switch (reduces to either limiter per regime); irregular meshes
 (conservation, per-cell divergence, second order on stretched meshes, exact
-face interpolation of a linear shear, reduction to the uniform mesh).
+face interpolation of a linear shear, reduction to the uniform mesh, the
+closed-form diagnostics of a uniform state: volume, face areas, zero
+divergence).
 
 Parity unpinned (readings the paper does not fix and no pin can separate):
 the exact directional fast speed in the freezing speed, the interface-local
