@@ -303,6 +303,33 @@ def bench_batch(args, torch, fish, fi):
         "note": "a box whose state fails the check (the scheme has no floors) stops with dt = 0 but stays "
                 "in every launch, so the timed work per step is constant",
     }
+    if not args.no_cpu:
+        # the oracle on 16 boxes of each edge, one double step each
+        from oracle import Oracle
+
+        cores = len(os.sched_getaffinity(0))
+        per_edge = {}
+        csample = []
+        for j in jobs:
+            e = j["n"][0]
+            if per_edge.get(e, 0) < 16:
+                per_edge[e] = per_edge.get(e, 0) + 1
+                csample.append(j)
+        log(f"CPU oracle baseline: one step of {len(csample)} boxes")
+        ccells, ctime = 0, 0.0
+        for job, st in _gen_states(fi, csample, args.workers):
+            o = Oracle(*job["n"], cfl=0.5, nthreads=cores)
+            o.set_state(st)
+            t0 = time.perf_counter()
+            o.strang_step(0.0)
+            ctime += time.perf_counter() - t0
+            ccells += job["n"][0] ** 3
+            o.close()
+        out["cpu_baseline"] = {"value": ccells / ctime, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+                               "sample": f"one double step of {len(csample)} of the boxes (16 per edge), FP64, "
+                                         f"{cores} OpenMP threads ({ctime:.1f} s)",
+                               "cpu_model": _cpu_model()}
+        log(f"  {out['cpu_baseline']['value']:.3e} cell-updates/s")
     print(json.dumps(out), flush=True)
 
 
@@ -415,7 +442,8 @@ def bench_sphere(args, torch, fish, fi):
     log(f"  {time.perf_counter() - t0:.1f} s")
     box = fish.Box(*n, precision="fp32", bc=(fish.OUTFLOW,) * 3, gravity=args.gravity, hse=True, cfl=0.5)
     box.set_state(st)
-    del st
+    if args.no_cpu:
+        del st
     for _ in range(args.warmup):
         box.strang_step(0.0)
     torch.cuda.synchronize()
@@ -457,6 +485,11 @@ def bench_sphere(args, torch, fish, fi):
                      "launches": launches, "algorithmic_bytes_per_launch": bytes_fluid},
         "state_ok": ok,
     }
+    if not args.no_cpu:
+        log("CPU oracle baseline: the first double step of the same box")
+        out["cpu_baseline"] = cpu_baseline(st, n, 0.5, 1, bc=(fish.OUTFLOW,) * 3, gravity=args.gravity, hse=True)
+        out["cpu_baseline"]["sample"] += " (a prefix of the 50-step run)"
+        log(f"  {out['cpu_baseline']['value']:.3e} cell-updates/s")
     print(json.dumps(out), flush=True)
 
 
