@@ -157,13 +157,13 @@ int fish_diagnostics(fish_ctx* ctx, double* out10);
 /* Irregular Cartesian mesh (Sect. 2.5): the widths of the n cells along axis
  * (0/1/2), host FP64 array of n values, all finite and > 0, copied.  From
  * then on every sweep and the CFL step use per-cell widths: the flux
- * differences of a cell divide by its own width (Eq. 37), the second-order
+ * differences of a cell divide by its own width (Eq. 69), the second-order
  * slopes divide each difference by the distance of its two cell centres and
  * are carried half a cell width to the interface, the gravity gradient spans
  * the two neighbouring centres, the face velocity of Eq. (65) interpolates
  * linearly between the two cell centres, the constraint update (Eq. 64) uses
  * the widths of the face's cell, and the CFL step takes each cell's widths
- * (Eq. 42).  Ghost cells take the width of the cell they map to.  Axes not
+ * (Eq. 70).  Ghost cells take the width of the cell they map to.  Axes not
  * set keep the uniform width of fish_params.  The widths reach the device
  * at the next call that steps, after the stream has drained.
  * FISH_ERR_ARG for a bad axis, a null array or a width that is not finite
@@ -312,6 +312,11 @@ int fish_batch_get(fish_batch* b, int id, double* cell5, double* bx, double* by,
 /* Time, last dt and the sticky state flag of one box.  Synchronises. */
 int fish_batch_box_info(fish_batch* b, int id, double* t_out, double* dt_out, int* bad_out);
 
+/* Double steps taken with dt > 0 by one box since its state was set (a box
+ * whose state went bad, or one that reached its end time, stops counting):
+ * the work a throughput figure may credit to the box.  Synchronises. */
+int fish_batch_box_steps(fish_batch* b, int id, int* steps_out);
+
 /* nsteps double steps of every box, each with its own CFL step.
  * Asynchronous. */
 int fish_batch_step(fish_batch* b, int nsteps);
@@ -385,7 +390,8 @@ int fish_server_submit(fish_server* s, const fish_request* r);
 int fish_server_pump(fish_server* s, int64_t* done_tags, int32_t* done_status, int max_done, int* ndone);
 
 /* Queue length, resident boxes, free pool bytes and cells x double steps
- * advanced so far (any pointer may be NULL). */
+ * enqueued so far, counting a box whose state went bad (it stops with dt = 0)
+ * until it retires (any pointer may be NULL). */
 int fish_server_stats(const fish_server* s, int* queued, int* resident, size_t* pool_free,
                       int64_t* cell_steps);
 

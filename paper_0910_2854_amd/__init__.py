@@ -96,7 +96,7 @@ EXPORTS = ("fish_create", "fish_destroy", "fish_last_error", "fish_set_state", "
            "fish_timing_enable", "fish_timing_read", "fish_selftest_lane_shift", "fish_autotune",
            "fish_box_pool_bytes", "fish_batch_create", "fish_batch_destroy", "fish_batch_last_error",
            "fish_batch_device_bytes", "fish_batch_free_bytes", "fish_batch_count", "fish_batch_add",
-           "fish_batch_remove", "fish_batch_get", "fish_batch_box_info", "fish_batch_step",
+           "fish_batch_remove", "fish_batch_get", "fish_batch_box_info", "fish_batch_box_steps", "fish_batch_step",
            "fish_batch_use_graph", "fish_batch_autotune", "fish_batch_sync", "fish_batch_timing_enable",
            "fish_batch_timing_read", "fish_set_shape", "fish_batch_set_shape", "fish_server_create", "fish_server_destroy", "fish_server_last_error",
            "fish_server_batch", "fish_server_submit", "fish_server_pump", "fish_server_stats", "fish_set_spacing",
@@ -117,6 +117,20 @@ def gravity_mode(gravity):
 _lib = None
 
 
+def hip_runtimes_loaded():
+    """Resolved paths of the HIP runtimes (libamdhip64) mapped into this process."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) >= 6 and "libamdhip64" in parts[-1]:
+                    paths.add(os.path.realpath(parts[-1]))
+    except OSError:  # pragma: no cover - not Linux
+        pass
+    return sorted(paths)
+
+
 def load_library(path: str = LIB_PATH):
     """Load libfish.so (raises if it has not been built)."""
     global _lib
@@ -124,11 +138,22 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
-    try:  # torch first: its HIP runtime is then the one the library resolves to, in every process
+    # PyTorch first.  Its wheel ships a HIP runtime of its own (torch/lib/
+    # libamdhip64.so, SONAME libamdhip64.so.7, which its libraries request
+    # under the unversioned name through their RPATH).  The library requests
+    # the SONAME libamdhip64.so.7, so with PyTorch loaded the dynamic linker
+    # binds it to PyTorch's runtime, the one that owns the caching allocator's
+    # memory and the streams handed to it.  Loaded before PyTorch, it would
+    # bind the system runtime and PyTorch would then map a second copy.
+    try:
         import torch  # noqa: F401
     except ImportError:  # pragma: no cover - the library still runs with hipMalloc and raw streams
         pass
     lib = ctypes.CDLL(path)
+    runtimes = hip_runtimes_loaded()
+    if len(runtimes) > 1:
+        raise ImportError("two HIP runtimes are loaded in this process (" + ", ".join(runtimes) + "); "
+                          "libfish.so was loaded before PyTorch: import torch (or this package) first")
     P, d, vp = ctypes.POINTER, ctypes.c_double, ctypes.c_void_p
     lib.fish_create.argtypes = [P(Params), P(vp)]
     lib.fish_destroy.argtypes = [vp]
@@ -165,6 +190,7 @@ def load_library(path: str = LIB_PATH):
     lib.fish_batch_remove.argtypes = [vp, ctypes.c_int]
     lib.fish_batch_get.argtypes = [vp, ctypes.c_int, P(d), P(d), P(d), P(d), P(d)]
     lib.fish_batch_box_info.argtypes = [vp, ctypes.c_int, P(d), P(d), P(ctypes.c_int)]
+    lib.fish_batch_box_steps.argtypes = [vp, ctypes.c_int, P(ctypes.c_int)]
     lib.fish_batch_step.argtypes = [vp, ctypes.c_int]
     lib.fish_batch_use_graph.argtypes = [vp, ctypes.c_int]
     lib.fish_batch_autotune.argtypes = [vp, ctypes.c_int, i32p]
@@ -195,7 +221,8 @@ def load_library(path: str = LIB_PATH):
     for name in ("fish_create", "fish_set_state", "fish_get_state", "fish_cfl_dt", "fish_strang_step",
                  "fish_sweep", "fish_diagnostics", "fish_timing_enable", "fish_timing_read", "fish_autotune",
                  "fish_batch_create", "fish_batch_count", "fish_batch_add", "fish_batch_remove", "fish_batch_get",
-                 "fish_batch_box_info", "fish_batch_step", "fish_batch_use_graph", "fish_batch_autotune",
+                 "fish_batch_box_info", "fish_batch_box_steps", "fish_batch_step", "fish_batch_use_graph",
+                 "fish_batch_autotune",
                  "fish_batch_sync", "fish_batch_timing_enable", "fish_batch_timing_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -537,6 +564,12 @@ class Batch:
         self._check(self._lib.fish_batch_box_info(self._h, int(box_id), ctypes.byref(t), ctypes.byref(dt),
                                                   ctypes.byref(bad)))
         return {"t": t.value, "dt": dt.value, "bad": bool(bad.value)}
+
+    def steps_taken(self, box_id):
+        """Double steps the box took with dt > 0 since its state was set."""
+        n = ctypes.c_int()
+        self._check(self._lib.fish_batch_box_steps(self._h, int(box_id), ctypes.byref(n)))
+        return n.value
 
     def step(self, nsteps=1):
         self._check(self._lib.fish_batch_step(self._h, int(nsteps)))

@@ -2,12 +2,17 @@
 // (engine.h): argument validation, the single-box context (an engine holding
 // one box) and the batch of many boxes.  No arithmetic of the scheme runs
 // here.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
+#include <link.h>
 
+#include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/fish.h"
 #include "batch.h"
@@ -47,6 +52,52 @@ double cmax_of(const Scalars& s) {
 namespace {
 // message of the last failed fish_create / fish_batch_create on this thread
 thread_local std::string g_create_err;
+
+// ------------------------------------------------ which HIP runtime
+// A process can hold two copies of the HIP runtime (libamdhip64): PyTorch
+// wheels ship their own, found through their RPATH under the unversioned
+// name libamdhip64.so, while this library asks for the SONAME
+// libamdhip64.so.7.  The dynamic linker reuses a loaded copy whose SONAME
+// matches, so the library binds to PyTorch's runtime when PyTorch is loaded
+// first; loaded before PyTorch it binds to the system runtime, and PyTorch
+// then maps its own copy next to it.  Streams and device memory belong to
+// the runtime that made them, so a stream or allocator callback from the
+// other copy cannot work here.
+std::string resolved(const char* name) {
+  char buf[PATH_MAX];
+  return realpath(name, buf) ? std::string(buf) : std::string(name);
+}
+
+int collect_runtime(struct dl_phdr_info* info, size_t, void* data) {
+  auto* v = static_cast<std::vector<std::string>*>(data);
+  const char* name = info->dlpi_name;
+  if (!name || !*name || !std::strstr(name, "libamdhip64")) return 0;
+  const std::string path = resolved(name);
+  for (const auto& s : *v)
+    if (s == path) return 0;
+  v->push_back(path);
+  return 0;
+}
+
+// 0 when the caller's stream or allocator can belong to this library's
+// runtime; FISH_ERR_DEVICE with a message when another HIP runtime is loaded
+// in the process and the caller passes either (checked before any HIP call).
+int check_runtime(const void* stream, bool has_alloc, std::string* msg) {
+  if (!stream && !has_alloc) return FISH_OK;  // everything is made by this library's runtime
+  std::vector<std::string> loaded;
+  dl_iterate_phdr(collect_runtime, &loaded);
+  if (loaded.size() <= 1) return FISH_OK;
+  Dl_info di;
+  std::string own = "?";
+  if (dladdr(reinterpret_cast<void*>(&hipGetDeviceCount), &di) && di.dli_fname) own = resolved(di.dli_fname);
+  std::string others;
+  for (const auto& s : loaded)
+    if (s != own) others += (others.empty() ? "" : ", ") + s;
+  *msg = "this library uses the HIP runtime " + own + ", but the process has also loaded " + others +
+         "; a stream or allocator of that runtime cannot be used here.  Load this library after the runtime "
+         "that owns them (with PyTorch: import torch first), or pass stream = NULL and alloc = NULL";
+  return FISH_ERR_DEVICE;
+}
 }  // namespace
 
 extern "C" {
@@ -63,6 +114,7 @@ int fish_create(const fish_params* p, fish_ctx** out) {
   if (Engine::validate_box(n, h, bc, p->cfl)) return FISH_ERR_ARG;
   if (check_common(p->gamma, p->limiter, p->predictor_alpha, p->precision, p->gravity, p->hse)) return FISH_ERR_ARG;
   if ((p->alloc == nullptr) != (p->free == nullptr)) return FISH_ERR_ARG;
+  if (check_runtime(p->stream, p->alloc != nullptr, &g_create_err)) return FISH_ERR_DEVICE;
   const long long cells = (long long)n[0] * n[1] * n[2];
   if (cells > (1ll << 34)) return FISH_ERR_ARG;
   const size_t esize = p->precision == FISH_FP64 ? 8 : 4;
@@ -271,6 +323,7 @@ int fish_batch_create(const fish_batch_params* p, fish_batch** out) {
   if (check_common(p->gamma, p->limiter, p->predictor_alpha, p->precision, p->gravity, p->hse)) return FISH_ERR_ARG;
   if ((p->alloc == nullptr) != (p->free == nullptr)) return FISH_ERR_ARG;
   if (p->max_boxes < 1 || p->max_boxes > (1 << 20)) return FISH_ERR_ARG;
+  if (check_runtime(p->stream, p->alloc != nullptr, &g_create_err)) return FISH_ERR_DEVICE;
   const size_t esize = p->precision == FISH_FP64 ? 8 : 4;
   const size_t per_elem = esize * (16 + (p->gravity ? 1 : 0));
   const long long cap = (long long)(p->pool_bytes / per_elem);
@@ -393,6 +446,16 @@ int fish_batch_box_info(fish_batch* b, int id, double* t_out, double* dt_out, in
   if (t_out) *t_out = s.t;
   if (dt_out) *dt_out = s.dt;
   if (bad_out) *bad_out = s.status;
+  return FISH_OK;
+}
+
+int fish_batch_box_steps(fish_batch* b, int id, int* steps_out) {
+  if (!b || !steps_out) return b ? b->e.fail(FISH_ERR_ARG, "null steps_out") : FISH_ERR_ARG;
+  if (id < 0 || id >= (int)b->e.boxes.size() || !b->e.boxes[id].used) return b->e.fail(FISH_ERR_ARG, "no such box");
+  Scalars s;
+  int rc = b->e.set_device();
+  if (rc || (rc = b->e.read_scalars(id, &s))) return rc;
+  *steps_out = s.taken;
   return FISH_OK;
 }
 

@@ -83,3 +83,49 @@ def test_batch_and_box_geometry_checks_without_a_device():
     h = ctypes.c_void_p()
     assert lib.fish_batch_create(ctypes.byref(bp), ctypes.byref(h)) == fish.FISH_ERR_ARG
     assert not h.value
+
+
+_TWO_RUNTIMES = r"""
+import ctypes, os, sys
+sys.path.insert(0, ROOT)
+lib = ctypes.CDLL(os.path.join(ROOT, "paper_0910_2854_amd", "libfish.so"))  # binds the system HIP runtime
+import torch  # noqa: F401  -- maps PyTorch's own copy next to it
+import paper_0910_2854_amd as fish
+p = fish.Params()
+p.nx = p.ny = p.nz = 8
+p.dx = p.dy = p.dz = 1.0 / 8
+p.gamma, p.cfl, p.limiter, p.predictor_alpha, p.precision = 5.0 / 3.0, 0.5, fish.VANLEER, 1.0, fish.FP64
+p.stream = 0x1000  # a stream handle of the caller: refused before any HIP call touches it
+lib.fish_create.argtypes = [ctypes.POINTER(fish.Params), ctypes.POINTER(ctypes.c_void_p)]
+lib.fish_last_error.argtypes = [ctypes.c_void_p]
+lib.fish_last_error.restype = ctypes.c_char_p
+h = ctypes.c_void_p()
+rc = lib.fish_create(ctypes.byref(p), ctypes.byref(h))
+print(rc, h.value)
+print(lib.fish_last_error(None).decode())
+print(len(fish.hip_runtimes_loaded()))
+"""
+
+
+def test_a_stream_of_another_hip_runtime_is_refused_with_a_message():
+    """Loaded before PyTorch, the library binds the system HIP runtime and
+    PyTorch maps its own copy; a caller's stream (or allocator) then belongs
+    to the other copy, and fish_create refuses it, naming both runtimes,
+    before any HIP call."""
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, "-c", "ROOT = %r\n" % ROOT + _TWO_RUNTIMES], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr[-3000:]
+    rc_line, msg, nrt = r.stdout.strip().splitlines()[-3:]
+    assert rc_line.split()[0] == str(fish.FISH_ERR_DEVICE) and rc_line.split()[1] == "None"
+    assert int(nrt) == 2
+    assert msg.count("libamdhip64") == 2 and "import torch first" in msg
+
+
+def test_the_binding_maps_one_hip_runtime():
+    """Through the binding, PyTorch is loaded first and the library binds its
+    runtime: one copy of libamdhip64 in the process."""
+    fish.load_library()
+    assert len(fish.hip_runtimes_loaded()) == 1
