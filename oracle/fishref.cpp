@@ -318,7 +318,7 @@ void fluid_pencil(const Pencil& P, int n, int d, double dt, double h, const doub
   for (int m = G - 2; m < G + n + 2; ++m) {
     double S[5] = {0, 0, 0, 0, 0};
     if (grav) gravity_source(C0[m].u, d, P.phi[m + 1] - P.phi[m - 1], span_of(hs, m, h), S);
-    const double hm = hs ? hs[m] : h;  // Eq. (37) on an irregular mesh
+    const double hm = hs ? hs[m] : h;  // Eq. (69) on an irregular mesh
     for (int k = 0; k < 5; ++k)
       up[k][m] = P.u[k][m] - dt / (2.0 * hm) * (F1[k][m] - F1[k][m - 1]) + 0.5 * dt * S[k];
   }
@@ -646,7 +646,7 @@ int cfl(Ctx* c, double* dt_out) {
           if (c->n[d] == 1) continue;
           CellQ q = cell_quantities(u, b, d, c->p.gamma);
           if (!(q.p > 0.0) || !(u[RHO] > 0.0) || !std::isfinite(q.d)) bad = true;
-          // Eq. (42) on an irregular mesh: the width of this cell along d
+          // Eq. (70) on an irregular mesh: the width of this cell along d
           const int idx[3] = {i, j, k};
           const double hd = c->nonuniform ? c->hs[d][idx[d] + G] : c->h[d];
           cmax = std::max(cmax, (std::fabs(q.vd) + q.cF) / hd);

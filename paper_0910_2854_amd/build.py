@@ -1,29 +1,60 @@
-"""Build the HIP library libfish.so for gfx950 (in-tree, next to this file)."""
+"""Build the HIP library libfish.so for gfx950 (in-tree, next to this file).
+
+Each translation unit of csrc/ is compiled to an object of its own, in
+parallel (the sweep kernels are split by precision and kind across the
+launch_*.hip units), and the objects are linked into the shared library.
+"""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfish.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fish.hip", "engine.hip", "server.hip")]
+OBJDIR = os.path.join(ROOT, "_build", "fish")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay off (see the design notes)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    cmd = [HIPCC, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-o", LIB + ".tmp", *SOURCES]
+def sources():
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+
+
+def build(verbose: bool = False, extra=(), out: str = LIB, jobs: int = 0) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+    srcs = sources()
+    tag = os.path.basename(out).replace(".so", "")
+    jobs = jobs or min(len(srcs), max(1, len(os.sched_getaffinity(0))))
+
+    def compile_one(src):
+        obj = os.path.join(OBJDIR, f"{tag}.{os.path.basename(src)}.o")
+        cmd = [HIPCC, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
+        if msg.strip():
+            print(msg, flush=True)
+        if r.returncode != 0:
+            raise subprocess.CalledProcessError(r.returncode, cmd)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(compile_one, srcs))
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out + ".tmp", *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

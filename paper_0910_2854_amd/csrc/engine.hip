@@ -4,6 +4,8 @@
 // a HIP graph, and the autotuner of the work-list shapes.
 #include "engine.h"
 
+#include "launch.h"
+#include "step_kernels.h"
 #include "sweeps.h"
 
 #include <algorithm>
@@ -16,16 +18,7 @@ namespace fish {
 
 namespace {
 
-constexpr int kBlock = 256;
 constexpr long long kAlign = 64;  // box offsets in elements (256 B in FP32)
-
-unsigned grid_for(long long threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
-
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess) return fail(3, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
 
 }  // namespace
 
@@ -40,21 +33,6 @@ Tuning default_tuning() {
   return t;
 }
 
-// Bracket one kernel launch with events when its class is being timed
-// (classes: 1 fluid, 2 field, 8 CFL check).
-struct TimedLaunch {
-  Engine* e;
-  int idx = -1;
-  TimedLaunch(Engine* eng, int cls) : e(eng) {
-    if ((e->timing_mask & cls) && e->ev_used < e->timing_max) {
-      idx = e->ev_used++;
-      (void)hipEventRecord(e->ev_start[idx], e->cfg.stream);
-    }
-  }
-  ~TimedLaunch() {
-    if (idx >= 0) (void)hipEventRecord(e->ev_stop[idx], e->cfg.stream);
-  }
-};
 
 Engine::~Engine() { release(); }
 
@@ -685,6 +663,10 @@ int Engine::build_lists() {
     }
     d.off = b.off;
     d.cfl = b.cfl;
+    for (int a = 0; a < 3; ++a) {
+      d.ih[a] = 1.0 / b.h[a];
+      d.i2h[a] = 1.0 / (2.0 * b.h[a]);
+    }
     d.slot = slots[t];
     for (int a = 0; a < 3; ++a) d.woff[a] = b.woff[a];
     const Tuning defaults = default_tuning();
@@ -697,6 +679,10 @@ int Engine::build_lists() {
         return fail(5, "work list exceeds the launch size");
       d.wave0[k] = (int)list[k].size();
       d.par[k] = par;
+      if (k == K_FLUID_Y || k == K_FLUID_Z || k == K_FIELD_Y || k == K_FIELD_Z) {
+        const int ax = (k == K_FLUID_Y || k == K_FIELD_Y) ? 1 : 2;
+        d.nseg[k] = (b.n[ax] + par - 1) / par;
+      }
       list[k].insert(list[k].end(), (size_t)w, t);
     }
   }
@@ -756,120 +742,6 @@ int Engine::build_lists() {
 
 int Engine::ensure_table() { return dirty ? build_lists() : 0; }
 
-static WorkList make_wl(const Engine* e, int kind) {
-  WorkList w;
-  w.boxes = static_cast<const BoxDesc*>(e->table.ptr);
-  w.wave_box = static_cast<const int*>(e->lists[kind].ptr);
-  w.nwaves = e->nwaves[kind];
-  w.xcd_remap = e->tuning.remap[kind];
-  w.row_groups = e->tuning.groups[kind];
-  return w;
-}
-
-// ------------------------------------------------------------ sub-operators
-template <typename T, int D, int GRAV, bool HSE, int LIM>
-void Engine::launch_fluid_mesh() {
-  if (nonuniform)
-    launch_fluid<T, D, GRAV, HSE, LIM, true>();
-  else
-    launch_fluid<T, D, GRAV, HSE, LIM, false>();
-}
-
-template <typename T, int D, int GRAV, bool HSE, int LIM, bool NU>
-void Engine::launch_fluid() {
-  FluidLaunch<T> L;
-  for (int k = 0; k < 5; ++k) {
-    L.u[k] = (const T*)pool[cur[k]][k].ptr;
-    L.uo[k] = (T*)pool[1 - cur[k]][k].ptr;
-  }
-  for (int k = 0; k < 3; ++k) L.b[k] = (const T*)pool[cur[5 + k]][5 + k].ptr;
-  L.phi = (const T*)phi.ptr;
-  for (int k = 0; k < 3; ++k) L.wid[k] = NU ? (const T*)wid[k].ptr : nullptr;
-  L.gamma = cfg.gamma;
-  L.alpha = cfg.alpha;
-  L.wl = make_wl(this, K_FLUID_X + D);
-  L.sc = (Scalars*)scal.ptr;
-  if (L.wl.nwaves == 0) return;
-  const dim3 grid(grid_for((long long)L.wl.nwaves * 64));
-  TimedLaunch tl(this, 1);
-  if (D == 0) {
-    if (last_fluid_cfl)
-      hipLaunchKernelGGL((fluid_lanes_kernel<T, GRAV, HSE, LIM, true, NU>), grid, dim3(kBlock), 0, cfg.stream, L);
-    else
-      hipLaunchKernelGGL((fluid_lanes_kernel<T, GRAV, HSE, LIM, false, NU>), grid, dim3(kBlock), 0, cfg.stream, L);
-  } else {
-    constexpr int DD = D == 0 ? 1 : D;
-    hipLaunchKernelGGL((fluid_strided_kernel<T, DD, GRAV, HSE, LIM, NU>), grid, dim3(kBlock), 0, cfg.stream, L);
-  }
-}
-
-template <typename T, int D, int LIM>
-void Engine::fluid_dispatch_lim() {
-  if (!cfg.gravity)
-    launch_fluid_mesh<T, D, 0, false, LIM>();
-  else if (cfg.gravity == 1)
-    cfg.hse ? launch_fluid_mesh<T, D, 1, true, LIM>() : launch_fluid_mesh<T, D, 1, false, LIM>();
-  else
-    cfg.hse ? launch_fluid_mesh<T, D, 2, true, LIM>() : launch_fluid_mesh<T, D, 2, false, LIM>();
-}
-
-template <typename T, int D>
-int Engine::fluid_dispatch() {
-  if (cfg.limiter == 0)
-    fluid_dispatch_lim<T, D, 0>();
-  else if (cfg.limiter == 1)
-    fluid_dispatch_lim<T, D, 1>();
-  else
-    fluid_dispatch_lim<T, D, 2>();
-  for (int k = 0; k < 5; ++k) cur[k] = 1 - cur[k];
-  return launch_check();
-}
-
-template <typename T, int D, int LIM>
-int Engine::field_sweep_lim() {
-  if (nonuniform)
-    launch_field<T, D, LIM, true>();
-  else
-    launch_field<T, D, LIM, false>();
-  for (int f = 5; f < 8; ++f) cur[f] = 1 - cur[f];
-  return launch_check();
-}
-
-template <typename T, int D, int LIM, bool NU>
-void Engine::launch_field() {
-  const int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
-  FieldLaunch<T> L;
-  L.rho = (const T*)pool[cur[0]][0].ptr;
-  L.md = (const T*)pool[cur[1 + D]][1 + D].ptr;
-  L.bt[0] = (const T*)pool[cur[5 + t1]][5 + t1].ptr;
-  L.bt[1] = (const T*)pool[cur[5 + t2]][5 + t2].ptr;
-  L.bd = (const T*)pool[cur[5 + D]][5 + D].ptr;
-  L.bto[0] = (T*)pool[1 - cur[5 + t1]][5 + t1].ptr;
-  L.bto[1] = (T*)pool[1 - cur[5 + t2]][5 + t2].ptr;
-  L.bdo = (T*)pool[1 - cur[5 + D]][5 + D].ptr;
-  for (int k = 0; k < 3; ++k) L.wid[k] = NU ? (const T*)wid[k].ptr : nullptr;
-  L.wl = make_wl(this, K_FIELD_X + D);
-  L.sc = (Scalars*)scal.ptr;
-  if (L.wl.nwaves > 0) {
-    const dim3 grid(grid_for((long long)L.wl.nwaves * 64));
-    TimedLaunch tl(this, 2);
-    if (D == 0) {
-      if (tuning.groups[K_FIELD_X] && !NU)  // two positions per lane: uniform meshes only
-        hipLaunchKernelGGL((field_lanes2_kernel<T, LIM>), grid, dim3(kBlock), 0, cfg.stream, L);
-      else
-        hipLaunchKernelGGL((field_lanes_kernel<T, LIM, NU>), grid, dim3(kBlock), 0, cfg.stream, L);
-    } else {
-      constexpr int DD = D == 0 ? 1 : D;
-      hipLaunchKernelGGL((field_strided_kernel<T, DD, LIM, NU>), grid, dim3(kBlock), 0, cfg.stream, L);
-    }
-  }
-}
-
-template <typename T, int D>
-int Engine::field_sweep() {
-  // the limiter switch (limiter 2) is a fluid choice: the field advection keeps van Leer
-  return cfg.limiter == 0 ? field_sweep_lim<T, D, 0>() : field_sweep_lim<T, D, 1>();
-}
 
 template <typename T>
 int Engine::sub_operator(int op, int d) {
@@ -1049,9 +921,8 @@ int Engine::strang_step(double dt) {
     if ((rc = enqueue_step_cfl())) return rc;
   } else {
     // a given step size (one box): every sub-operator of size dt
-    for (int s : table_slots) {
-      hipLaunchKernelGGL(set_dt_kernel, dim3(1), dim3(1), 0, cfg.stream, (Scalars*)scal.ptr + s, dt);
-    }
+    hipLaunchKernelGGL(set_dt_kernel, dim3(grid_for((long long)table_slots.size())), dim3(kBlock), 0, cfg.stream,
+                       (const BoxDesc*)table.ptr, (int)table_slots.size(), (Scalars*)scal.ptr, dt);
     if ((rc = launch_check())) return rc;
     for (int d = 0; d < 3; ++d) {
       if ((rc = run_sub(0, d))) return rc;
@@ -1190,7 +1061,11 @@ int Engine::sweep(int slot, int op, int dir, double dt) {
   int rc = set_device();
   if (rc) return rc;
   if ((rc = ensure_table())) return rc;
-  hipLaunchKernelGGL(set_dt_kernel, dim3(1), dim3(1), 0, cfg.stream, (Scalars*)scal.ptr + slot, dt);
+  // the sub-operator of one box: its step factors from its table entry
+  const auto it = std::find(table_slots.begin(), table_slots.end(), slot);
+  if (it == table_slots.end()) return fail(1, "the box has no state");
+  hipLaunchKernelGGL(set_dt_kernel, dim3(1), dim3(1), 0, cfg.stream,
+                     (const BoxDesc*)table.ptr + (it - table_slots.begin()), 1, (Scalars*)scal.ptr, dt);
   if ((rc = launch_check())) return rc;
   for (int s : table_slots) boxes[s].cfl_fresh = false;
   return run_sub(op, dir);

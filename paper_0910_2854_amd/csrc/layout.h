@@ -21,6 +21,7 @@ struct Scalars {
   int has_end;
   int taken;                    // double steps taken with dt > 0
   int pad;
+  double kh[3], kf[3];          // dt / (2 h_d) and dt / h_d per axis, set with dt
 };
 
 // ------------------------------------------------------------ work lists
@@ -37,8 +38,9 @@ struct BoxDesc {
   int slot;           // index of the box's Scalars
   int wave0[K_NUM];   // first wave of the box in each kind's list
   int par[K_NUM];     // rows per wave (x kinds), segment length (y/z kinds), cells per lane (check)
-  int pad;
+  int nseg[K_NUM];    // y/z kinds: segments per pencil, ceil(n_d / par)
   long long woff[3];  // irregular meshes: element offset of the box's cell widths in each axis's width array
+  double ih[3], i2h[3];  // 1 / h_d and 1 / (2 h_d)
 };
 
 struct WorkList {

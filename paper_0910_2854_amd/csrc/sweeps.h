@@ -161,35 +161,53 @@ __device__ __forceinline__ Vec<T, N> prev_vec(const Vec<T, N>& cur, const Vec<T,
 
 // ------------------------------------------------------------ lanes cursor
 // Position of one lane in the stream of whole rows a wave walks (lanes
-// policy): row rr of the wave's rows and position cp in [0, L) of that row.
-// Advancing by one iteration moves `step` positions (64, or 128 with two
-// positions per lane); the row indices (y, z) are stepped, never divided,
-// and stay on the wave's last row past its end (those lanes' positions are
-// beyond the stream and write nothing).
+// policy): row rr of the wave's rows and position cp in [0, L) of that row,
+// with the row's transverse indices (y, z) and its element offset base =
+// y st1 + z st2.  Advancing by one iteration moves `step` positions (64, or
+// 128 with two positions per lane); the row indices and the offset are
+// stepped, never divided or multiplied, and stay on the wave's last row past
+// its end (those lanes' positions are beyond the stream and write nothing).
+// nrow is the number of rows per plane (cells, or face rows of the field
+// sweep).
 struct RowCursor {
   int cp, rr, y, z;
+  unsigned base;
   bool moved;
-  __device__ void init(int pos, int L, long long r0, int rows, int ny) {
+  // r0 (the wave's first row) is uniform across the wave: one division per
+  // wave, then the lane's own rows are stepped.  up: the element offset from
+  // the last row of a plane to the first row of the next one, st2 - (nrow - 1) st1.
+  __device__ void init(int pos, int L, int r0, int rows, int nrow, unsigned st1, unsigned st2, unsigned up) {
+    const int z0 = r0 / nrow, y0 = r0 - z0 * nrow;
     cp = pos;
     rr = 0;
+    y = y0;
+    z = z0;
+    base = (unsigned)y0 * st1 + (unsigned)z0 * st2;
+    moved = true;
     while (cp >= L && rr < rows - 1) {
       cp -= L;
       ++rr;
+      if (++y == nrow) {
+        y = 0;
+        ++z;
+        base += up;
+      } else {
+        base += st1;
+      }
     }
-    const long long row = r0 + rr;
-    y = (int)(row % ny);
-    z = (int)(row / ny);
-    moved = true;
   }
-  __device__ void advance(int L, int rows, int ny, int step = 64) {
+  __device__ void advance(int L, int rows, int nrow, unsigned st1, unsigned up, int step = 64) {
     cp += step;
     moved = false;
     while (cp >= L && rr < rows - 1) {
       cp -= L;
       ++rr;
-      if (++y == ny) {
+      if (++y == nrow) {
         y = 0;
         ++z;
+        base += up;
+      } else {
+        base += st1;
       }
       moved = true;
     }
@@ -200,11 +218,14 @@ struct RowCursor {
 // [-8, n + 4): a clamp on outflow axes, at most one period added or removed
 // on periodic ones (boxes thinner than 8 cells take the general wrap).  bc and
 // n are uniform across the wave, so the choice of path is a scalar branch.
+// The periodic map is the smallest of i, i + n and i - n as unsigned values
+// (one of them lies in [0, n), the others are larger or negative), which is
+// one three-way minimum.
 __device__ __forceinline__ int map_cell_near(int i, int n, int bc) {
   if (bc) return min(max(i, 0), n - 1);
   if (n >= 8) {
-    i += i < 0 ? n : 0;
-    return i >= n ? i - n : i;
+    const unsigned a = (unsigned)i, b = (unsigned)(i + n), c = (unsigned)(i - n);
+    return (int)min(a, min(b, c));
   }
   return wrap(i, n);
 }
@@ -226,6 +247,7 @@ struct FluidArgs {
   int seg, nseg;   // strided: segment length along D and segments per pencil
   int rows_per_wave; // lanes: whole rows per wave
   const Scalars* sc;
+  double i2h[3];     // 1 / (2 h_d)
 };
 
 // Kernel arguments of a fluid sweep over a batch: the pools and the list.
@@ -262,9 +284,12 @@ __device__ __forceinline__ FluidArgs<T> fluid_view(const FluidLaunch<T>& L, cons
   a.alpha = L.alpha;
   const int D = KIND - K_FLUID_X;
   a.seg = d.par[KIND];
-  a.nseg = (d.g.n[D] + a.seg - 1) / a.seg;
+  a.nseg = d.nseg[KIND];
   a.rows_per_wave = d.par[KIND];
   a.sc = L.sc + d.slot;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) a.i2h[i] = d.i2h[i];
+  (void)D;
   return a;
 }
 
@@ -377,7 +402,7 @@ __device__ __forceinline__ void fluid_position(const T* uc_in, const Vec<T, 3>& 
 #pragma unroll
   for (int i = 0; i < 5; ++i) F1.v[i] = T(0.5) * (q0m.F[i] + q0.F[i]) - k.halfalpha * Q[i];
   const Vec<T, 5> F1m = prev_vec<H>(F1, hi.F1, ho.F1);
-  // predictor half step of cell c-1 (Eq. 41; Eq. 37 on an irregular mesh)
+  // predictor half step of cell c-1 (Eq. 41; Eq. 69 on an irregular mesh)
   T up[5];
   const T khalf = NU ? nu.kh1 : k.k_half;
   if (GRAV == 1) {
@@ -467,16 +492,17 @@ __device__ __forceinline__ void fluid_position(const T* uc_in, const Vec<T, 3>& 
   (void)phm3;
 }
 
+// The step factors of a sweep along D: dt / (2h) and dt / h from the box's
+// step scalars (evaluated once per step with dt), 1 / (2h) from its table entry.
 template <typename T>
 __device__ __forceinline__ FluidConsts<T> fluid_consts(const FluidArgs<T>& a, int D) {
   const double dt = a.sc->dt;
-  const double h = a.g.h[D];
   FluidConsts<T> k;
-  k.k_half = (T)(dt / (2.0 * h));
-  k.k_full = (T)(dt / h);
+  k.k_half = (T)a.sc->kh[D];
+  k.k_full = (T)a.sc->kf[D];
   k.half_dt = (T)(0.5 * dt);
   k.dt = (T)dt;
-  k.inv2h = (T)(1.0 / (2.0 * h));
+  k.inv2h = (T)a.i2h[D];
   k.halfalpha = (T)(0.5 * a.alpha);
   k.gamma = a.gamma;
   return k;
@@ -661,7 +687,7 @@ __device__ __forceinline__ double cfl_of(const double* smax, const Geo& g) {
   return c;
 }
 
-// Eq. (42), the CFL condition on an irregular mesh: max over the active axes
+// Eq. (70), the CFL condition on an irregular mesh: max over the active axes
 // of one cell's speed over its own width along that axis.
 __device__ __forceinline__ double cfl_of_cell(const double* sp, double wx, double wy, double wz, const Geo& g) {
   const double w[3] = {wx, wy, wz};
@@ -719,11 +745,17 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
   double smax[3] = {0.0, 0.0, 0.0};
   double cnu = 0.0;  // irregular mesh: the CFL speed over widths, per cell
   int bad = 0;
+  const unsigned st1 = (unsigned)g.st[1], st2 = (unsigned)g.st[2];  // arrays < 2^32 bytes
+  const unsigned up = st2 - (unsigned)(ny - 1) * st1;
   RowCursor rc;
-  rc.init(lane - HALO, L, r0, rows, ny);  // the halo lanes start before the stream (clamped to its start)
-  unsigned base = 0, dy = 0, dz = 0;  // row offsets (elements; arrays < 2^31 elements)
-  T wy = T(1), wz = T(1);             // irregular mesh: widths of the row's cell in y, z
+  rc.init(lane - HALO, L, (int)r0, rows, ny, st1, st2, up);  // the halo lanes start before the stream (clamped to its start)
   constexpr unsigned z4 = sizeof(T);
+  // byte offsets of the face above the row's cells along y and z: the next
+  // row or plane, or on a periodic axis from the last one back to the first
+  const unsigned dy_in = st1 * z4, dy_last = g.bc[1] ? dy_in : (unsigned)(1 - ny) * st1 * z4;
+  const unsigned dz_in = st2 * z4, dz_last = g.bc[2] ? dz_in : (unsigned)(1 - nz) * st2 * z4;
+  unsigned base = 0, dy = 0, dz = 0;  // the row's offset (elements) and face offsets (bytes)
+  T wy = T(1), wz = T(1);             // irregular mesh: widths of the row's cell in y, z
   struct In {
     T u[5], u3[5];
     Vec<T, 3> bc;
@@ -738,9 +770,9 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
   auto load = [&](int it) {
     if (rc.moved) {
       const int y = rc.y, z = rc.z;
-      base = (unsigned)((long long)y * g.st[1] + (long long)z * g.st[2]);
-      dy = (unsigned)((long long)(map_face_near(y + 1, ny, g.bc[1]) - y) * g.st[1]) * z4;
-      dz = (unsigned)((long long)(map_face_near(z + 1, nz, g.bc[2]) - z) * g.st[2]) * z4;
+      base = rc.base;
+      dy = y + 1 < ny ? dy_in : dy_last;
+      dz = z + 1 < nz ? dz_in : dz_last;
       if (NU) {
         wy = width_at(a.wid[1], y, ny, g.bc[1]);
         wz = width_at(a.wid[2], z, nz, g.bc[2]);
@@ -791,7 +823,7 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
       in.b3[1] = T(0.5) * (ld(a.b[1], in.o3) + ld(a.b[1], in.o3 + dy));
       in.b3[2] = T(0.5) * (ld(a.b[2], in.o3) + ld(a.b[2], in.o3 + dz));
     }
-    rc.advance(L, rows, ny, STEP);
+    rc.advance(L, rows, ny, st1, up, STEP);
     return in;
   };
   auto compute = [&](const In& in, const FluidHist<T, HSE>& hi, FluidHist<T, HSE>& ho) {
@@ -848,6 +880,7 @@ struct FieldArgs {
   int seg, nseg;           // strided policy
   int rows_per_wave;       // lanes policy
   const Scalars* sc;
+  double ih[3];            // 1 / h_d
 };
 
 template <typename T>
@@ -880,9 +913,12 @@ __device__ __forceinline__ FieldArgs<T> field_view(const FieldLaunch<T>& L, cons
   a.g = d.g;
   const int D = KIND - K_FIELD_X;
   a.seg = d.par[KIND];
-  a.nseg = (d.g.n[D] + a.seg - 1) / a.seg;
+  a.nseg = d.nseg[KIND];
   a.rows_per_wave = d.par[KIND];
   a.sc = L.sc + d.slot;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) a.ih[i] = d.ih[i];
+  (void)D;
   return a;
 }
 
@@ -957,16 +993,16 @@ struct FieldConsts {
   T k_half, k_full, dt, ih1, ih2;
 };
 
+// The step factors of a field sweep along D (see fluid_consts).
 template <typename T, int D>
 __device__ __forceinline__ FieldConsts<T> field_consts(const FieldArgs<T>& a) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  const double dt = a.sc->dt;
   FieldConsts<T> k;
-  k.k_half = (T)(dt / (2.0 * a.g.h[D]));
-  k.k_full = (T)(dt / a.g.h[D]);
-  k.dt = (T)dt;
-  k.ih1 = (T)(1.0 / a.g.h[T1]);
-  k.ih2 = (T)(1.0 / a.g.h[T2]);
+  k.k_half = (T)a.sc->kh[D];
+  k.k_full = (T)a.sc->kf[D];
+  k.dt = (T)a.sc->dt;
+  k.ih1 = (T)a.ih[T1];
+  k.ih2 = (T)a.ih[T2];
   return k;
 }
 
@@ -994,25 +1030,30 @@ __device__ __forceinline__ FieldOffsets field_offsets(const Geo& g, int c1, int 
   return o;
 }
 
-// The same offsets for the x sweep's rows (t1 = y, t2 = z) in 32-bit element
-// arithmetic, with the cheap maps (the neighbours are within one period).
+// The same offsets for the x sweep's rows (t1 = y, t2 = z), in bytes, with
+// the cheap maps (the neighbours are within one period); base is the face
+// row's element offset y st1 + z st2, which the lanes cursor keeps.
+// All in unsigned arithmetic: a difference that is negative wraps, and adding
+// it to an offset wraps back (every offset is below 2^32 bytes).
 struct RowOffsets {
   unsigned base, ownc;             // face row (c1, c2) and its mapped own cell
-  int c1m, c1p, c2m, c2p, f1p, f2p;
+  unsigned c1m, c1p, c2m, c2p, f1p, f2p;
 };
 
-__device__ __forceinline__ void row_offsets(const Geo& g, int c1, int c2, RowOffsets& r) {
-  const int st1 = (int)g.st[1], st2 = (int)g.st[2];
+template <typename T>
+__device__ __forceinline__ void row_offsets(const Geo& g, int c1, int c2, unsigned base, RowOffsets& r) {
+  constexpr unsigned z = sizeof(T);
+  const unsigned st1 = (unsigned)g.st[1], st2 = (unsigned)g.st[2];
   const int n1 = g.n[1], n2 = g.n[2], b1 = g.bc[1], b2 = g.bc[2];
   const int m1 = map_cell_near(c1, n1, b1), m2 = map_cell_near(c2, n2, b2);
-  r.base = (unsigned)(c1 * st1 + c2 * st2);
-  r.ownc = (unsigned)(m1 * st1 + m2 * st2);
-  r.c1m = (map_cell_near(c1 - 1, n1, b1) - m1) * st1;
-  r.c1p = (map_cell_near(c1 + 1, n1, b1) - m1) * st1;
-  r.c2m = (map_cell_near(c2 - 1, n2, b2) - m2) * st2;
-  r.c2p = (map_cell_near(c2 + 1, n2, b2) - m2) * st2;
-  r.f1p = (map_face_near(c1 + 1, n1, b1) - c1) * st1;
-  r.f2p = (map_face_near(c2 + 1, n2, b2) - c2) * st2;
+  r.base = base * z;
+  r.ownc = (base + (unsigned)(m1 - c1) * st1 + (unsigned)(m2 - c2) * st2) * z;
+  r.c1m = (unsigned)(map_cell_near(c1 - 1, n1, b1) - m1) * st1 * z;
+  r.c1p = (unsigned)(map_cell_near(c1 + 1, n1, b1) - m1) * st1 * z;
+  r.c2m = (unsigned)(map_cell_near(c2 - 1, n2, b2) - m2) * st2 * z;
+  r.c2p = (unsigned)(map_cell_near(c2 + 1, n2, b2) - m2) * st2 * z;
+  r.f1p = (unsigned)(map_face_near(c1 + 1, n1, b1) - c1) * st1 * z;
+  r.f2p = (unsigned)(map_face_near(c2 + 1, n2, b2) - c2) * st2 * z;
 }
 
 // Byte offsets of everything one position reads, relative to the arrays'
@@ -1045,6 +1086,7 @@ struct FieldIn {
   T md[5], rho[5];  // cells (c1, c2), (c1-1, c2), (c1+1, c2), (c1, c2-1), (c1, c2+1)
   T b[4];           // b_t1 at t1-faces c1, c1+1; b_t2 at t2-faces c2, c2+1
   T b4a, b4c;       // b_t1, b_t2 of cell c-4 (lanes policy)
+  T bd3;            // b_d at d-face c-3, which the constraint update of this position rewrites
 };
 
 template <typename T>
@@ -1061,7 +1103,7 @@ __device__ __forceinline__ FieldIn<T> field_load(const T* md, const T* rho, cons
   in.b[1] = ld(bt0, l.fB);
   in.b[2] = ld(bt1, l.fC);
   in.b[3] = ld(bt1, l.fD);
-  in.b4a = in.b4c = T(0);
+  in.b4a = in.b4c = in.bd3 = T(0);
   return in;
 }
 
@@ -1204,8 +1246,12 @@ __global__ __launch_bounds__(256) void field_strided_kernel(FieldLaunch<T> FL) {
   auto load = [&](int it) {
     const int s = s0 - 4 + it;  // uniform
     const long long off = (long long)map_cell(s, nD, g.bc[D]) * stD;
-    return field_load<T>(in_sgpr(a.md + off), in_sgpr(a.rho + off), in_sgpr(a.bt[0] + off), in_sgpr(a.bt[1] + off),
-                         l);
+    FieldIn<T> in = field_load<T>(in_sgpr(a.md + off), in_sgpr(a.rho + off), in_sgpr(a.bt[0] + off),
+                                  in_sgpr(a.bt[1] + off), l);
+    // b_d at d-face s-3, issued with the other loads (the constraint update
+    // of this position rewrites it); the mapped face is in range everywhere
+    in.bd3 = ld(in_sgpr(a.bd + (long long)map_face(s - 3, nD, g.bc[D]) * stD), l.fA);
+    return in;
   };
   auto compute = [&](int it, const FieldIn<T>& in, const RowHist<T>* hi, RowHist<T>* ho) {
     const int s = s0 - 4 + it;
@@ -1226,7 +1272,7 @@ __global__ __launch_bounds__(256) void field_strided_kernel(FieldLaunch<T> FL) {
     const int fd = s - 3;
     if (ownd && it >= 7 && (fd < s1 || (last && outD && fd == nD))) {
       const long long of = (long long)fd * stD;
-      st(in_sgpr(a.bdo + of), l.fA, ld(in_sgpr(a.bd + of), l.fA) + dbd);
+      st(in_sgpr(a.bdo + of), l.fA, in.bd3 + dbd);
     }
   };
   // positions s0-4 .. s1+3, padded to an even count (the pad writes nothing;
@@ -1275,8 +1321,10 @@ __global__ __launch_bounds__(256) void field_lanes_kernel(FieldLaunch<T> FL) {
   const int nit = (npos + STEP - 1) / STEP;
   const FieldConsts<T> k = field_consts<T, D>(a);
   RowHist<T> hA[4], hB[4];  // unused by the carry-free policy
+  const unsigned st1 = (unsigned)g.st[1], st2 = (unsigned)g.st[2];  // arrays < 2^32 bytes
+  const unsigned up = st2 - (unsigned)(ry - 1) * st1;
   RowCursor rc;
-  rc.init(lane - HALO, L, r0, rows, ry);  // the halo lanes start before the stream (clamped to its start)
+  rc.init(lane - HALO, L, (int)r0, rows, ry, st1, st2, up);  // the halo lanes start before the stream (clamped to its start)
   RowOffsets ro;
   bool own1 = false, own2 = false;
   FieldRowNU<T> rnr{};  // irregular mesh: the factors of the current row
@@ -1291,7 +1339,7 @@ __global__ __launch_bounds__(256) void field_lanes_kernel(FieldLaunch<T> FL) {
   constexpr unsigned z = sizeof(T);
   auto load = [&](int it) {
     if (rc.moved) {
-      row_offsets(g, rc.y, rc.z, ro);  // y, z face rows
+      row_offsets<T>(g, rc.y, rc.z, rc.base, ro);  // y, z face rows
       own1 = rc.z < g.n[2];
       own2 = rc.y < g.n[1];
       if (NU) {
@@ -1306,30 +1354,31 @@ __global__ __launch_bounds__(256) void field_lanes_kernel(FieldLaunch<T> FL) {
     in.cpos = min(max(rc.cp, 0), L - 1) - 4;  // cell index along x (-4 .. nx+3), clamped as in the fluid sweep
     in.own1 = own1;
     in.own2 = own2;
-    const unsigned mx = (unsigned)map_cell_near(in.cpos, nx, g.bc[0]);
-    const unsigned m4 = (unsigned)map_cell_near(in.cpos - 4, nx, g.bc[0]);
+    const unsigned xb = (unsigned)map_cell_near(in.cpos, nx, g.bc[0]) * z;
     FieldLane l;
-    const unsigned oc = ro.ownc + mx;
-    l.cc = oc * z;
-    l.c1m = (oc + ro.c1m) * z;
-    l.c1p = (oc + ro.c1p) * z;
-    l.c2m = (oc + ro.c2m) * z;
-    l.c2p = (oc + ro.c2p) * z;
-    l.fA = (ro.base + mx) * z;
-    l.fB = (ro.base + mx + ro.f1p) * z;
+    l.cc = ro.ownc + xb;
+    l.c1m = l.cc + ro.c1m;
+    l.c1p = l.cc + ro.c1p;
+    l.c2m = l.cc + ro.c2m;
+    l.c2p = l.cc + ro.c2p;
+    l.fA = ro.base + xb;
+    l.fB = l.fA + ro.f1p;
     l.fC = l.fA;
-    l.fD = (ro.base + mx + ro.f2p) * z;
+    l.fD = l.fA + ro.f2p;
     in.f = field_load<T>(a.md, a.rho, a.bt[0], a.bt[1], l);
-    in.b4off = (ro.base + m4) * z;
+    in.b4off = ro.base + (unsigned)map_cell_near(in.cpos - 4, nx, g.bc[0]) * z;
     in.f.b4a = ld(a.bt[0], in.b4off);
     in.f.b4c = ld(a.bt[1], in.b4off);
-    in.fo = (ro.base + (unsigned)max(in.cpos - 3, 0)) * z;
+    // d-face c-3 (mapped, in range for every lane); b_d there is rewritten by
+    // this position's constraint update, so it is loaded with the inputs
+    in.fo = ro.base + (unsigned)map_face_near(in.cpos - 3, nx, g.bc[0]) * z;
+    in.f.bd3 = ld(a.bd, in.fo);
     if (NU) {
       in.rn = rnr;
 #pragma unroll
       for (int j = 0; j < 4; ++j) in.w[j] = width_at(a.wid[0], in.cpos - 5 + j, nx, g.bc[0]);
     }
-    rc.advance(L, rows, ry, STEP);
+    rc.advance(L, rows, ry, st1, up, STEP);
     return in;
   };
   auto compute = [&](const In& in, const RowHist<T>* hi, RowHist<T>* ho) {
@@ -1343,7 +1392,7 @@ __global__ __launch_bounds__(256) void field_lanes_kernel(FieldLaunch<T> FL) {
     }
     const int fd = in.cpos - 3;
     if (in.valid && in.own1 && in.own2 && fd >= 0 && (fd < nx || (outx && fd == nx)))
-      st(a.bdo, in.fo, ld(a.bd, in.fo) + dbd);
+      st(a.bdo, in.fo, in.f.bd3 + dbd);
   };
   In cur = load(0);
   for (int it = 0; it < nit; it += 2) {
@@ -1436,11 +1485,13 @@ __global__ __launch_bounds__(256) void field_lanes2_kernel(FieldLaunch<T> FL) {
   constexpr int HALO = 8, STEP = 128 - HALO;  // positions
   const int nit = (npos + STEP - 1) / STEP;
   const FieldConsts<T> k = field_consts<T, D>(a);
+  const unsigned st1 = (unsigned)g.st[1], st2 = (unsigned)g.st[2];  // arrays < 2^32 bytes
+  const unsigned up = st2 - (unsigned)(ry - 1) * st1;
   RowCursor rc[2];
   RowOffsets ro[2];
   bool own1[2] = {false, false}, own2[2] = {false, false};
 #pragma unroll
-  for (int j = 0; j < 2; ++j) rc[j].init(2 * lane + j - HALO, L, r0, rows, ry);
+  for (int j = 0; j < 2; ++j) rc[j].init(2 * lane + j - HALO, L, (int)r0, rows, ry, st1, st2, up);
   constexpr unsigned z = sizeof(T);
   struct In {
     FieldIn<T> f;
@@ -1450,7 +1501,7 @@ __global__ __launch_bounds__(256) void field_lanes2_kernel(FieldLaunch<T> FL) {
   };
   auto load1 = [&](int it, int j) {
     if (rc[j].moved) {
-      row_offsets(g, rc[j].y, rc[j].z, ro[j]);
+      row_offsets<T>(g, rc[j].y, rc[j].z, rc[j].base, ro[j]);
       own1[j] = rc[j].z < g.n[2];
       own2[j] = rc[j].y < g.n[1];
     }
@@ -1459,25 +1510,24 @@ __global__ __launch_bounds__(256) void field_lanes2_kernel(FieldLaunch<T> FL) {
     in.cpos = min(max(rc[j].cp, 0), L - 1) - 4;  // clamped as in the fluid sweep
     in.own1 = own1[j];
     in.own2 = own2[j];
-    const unsigned mx = (unsigned)map_cell_near(in.cpos, nx, g.bc[0]);
-    const unsigned m4 = (unsigned)map_cell_near(in.cpos - 4, nx, g.bc[0]);
+    const unsigned xb = (unsigned)map_cell_near(in.cpos, nx, g.bc[0]) * z;
     FieldLane l;
-    const unsigned oc = ro[j].ownc + mx;
-    l.cc = oc * z;
-    l.c1m = (oc + ro[j].c1m) * z;
-    l.c1p = (oc + ro[j].c1p) * z;
-    l.c2m = (oc + ro[j].c2m) * z;
-    l.c2p = (oc + ro[j].c2p) * z;
-    l.fA = (ro[j].base + mx) * z;
-    l.fB = (ro[j].base + mx + ro[j].f1p) * z;
+    l.cc = ro[j].ownc + xb;
+    l.c1m = l.cc + ro[j].c1m;
+    l.c1p = l.cc + ro[j].c1p;
+    l.c2m = l.cc + ro[j].c2m;
+    l.c2p = l.cc + ro[j].c2p;
+    l.fA = ro[j].base + xb;
+    l.fB = l.fA + ro[j].f1p;
     l.fC = l.fA;
-    l.fD = (ro[j].base + mx + ro[j].f2p) * z;
+    l.fD = l.fA + ro[j].f2p;
     in.f = field_load<T>(a.md, a.rho, a.bt[0], a.bt[1], l);
-    in.b4off = (ro[j].base + m4) * z;
+    in.b4off = ro[j].base + (unsigned)map_cell_near(in.cpos - 4, nx, g.bc[0]) * z;
     in.f.b4a = ld(a.bt[0], in.b4off);
     in.f.b4c = ld(a.bt[1], in.b4off);
-    in.fo = (ro[j].base + (unsigned)max(in.cpos - 3, 0)) * z;
-    rc[j].advance(L, rows, ry, STEP);
+    in.fo = ro[j].base + (unsigned)map_face_near(in.cpos - 3, nx, g.bc[0]) * z;
+    in.f.bd3 = ld(a.bd, in.fo);
+    rc[j].advance(L, rows, ry, st1, up, STEP);
     return in;
   };
   auto compute = [&](const In (&in)[2]) {
@@ -1514,7 +1564,7 @@ __global__ __launch_bounds__(256) void field_lanes2_kernel(FieldLaunch<T> FL) {
       }
       const int fd = in[j].cpos - 3;
       if (in[j].valid && in[j].own1 && in[j].own2 && fd >= 0 && (fd < nx || (outx && fd == nx)))
-        st(a.bdo, in[j].fo, ld(a.bd, in[j].fo) + dbd);
+        st(a.bdo, in[j].fo, in[j].f.bd3 + dbd);
     }
   };
   for (int it = 0; it < nit; ++it) {
@@ -1603,178 +1653,6 @@ __global__ __launch_bounds__(256) void check_cfl_kernel(CheckLaunch<T> L) {
     }
   }
   publish_cfl(nu ? cnu : cfl_of(smax, g), bad, L.sc + d->slot);
-}
-
-// Per-box step scalars; one thread per box of the table.
-__global__ void reset_cmax_kernel(const BoxDesc* boxes, int nb, Scalars* sc) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nb) sc[boxes[i].slot].cmax_bits = 0ull;
-}
-
-// dt = k / cmax (Eq. 14); a bad reduction marks the state and stops the box.
-__global__ void finalize_dt_kernel(const BoxDesc* boxes, int nb, Scalars* sc) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  Scalars* s = sc + boxes[i].slot;
-  const double cmax = __longlong_as_double((long long)s->cmax_bits);
-  if (!(cmax > 0.0) || !isfinite(cmax) || s->status) {
-    s->status |= 1;
-    s->dt = 0.0;
-    return;
-  }
-  double dt = boxes[i].cfl / cmax;
-  if (s->has_end) {
-    // the double step advances 2 dt: no further than t_end (a step of
-    // (t_end - t)/2 lands on t_end exactly), none once it is reached
-    const double rest = s->t_end - s->t;
-    dt = rest > 0.0 ? fmin(dt, 0.5 * rest) : 0.0;
-  }
-  s->dt = dt;
-}
-
-__global__ void advance_time_kernel(const BoxDesc* boxes, int nb, Scalars* sc) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nb) {
-    Scalars* s = sc + boxes[i].slot;
-    if (s->dt > 0.0) {
-      s->t += 2.0 * s->dt;
-      s->taken += 1;
-    }
-  }
-}
-
-__global__ void set_dt_kernel(Scalars* sc, double dt) { sc->dt = dt; }
-__global__ void set_end_kernel(Scalars* sc, double t_end, int on) {
-  sc->t_end = t_end;
-  sc->has_end = on;
-}
-__global__ void set_scalars_kernel(Scalars* sc, double t, int status) {
-  sc->t = t;
-  sc->status = status;
-  sc->cmax_bits = 0ull;
-  sc->dt = 0.0;
-  sc->t_end = 0.0;
-  sc->has_end = 0;
-  sc->taken = 0;
-}
-
-// ------------------------------------------------------------ diagnostics
-template <typename T>
-struct DiagArgs {
-  const T* u[5];
-  const T* b[3];
-  const T* wid[3];   // irregular mesh: cell widths per axis (all three set), else null
-  Geo g;
-  double* partial;   // [nblocks][10]
-};
-
-// Per-block partial sums in a fixed order (deterministic): each block owns a
-// fixed contiguous range of cells; a fixed tree inside the block.
-template <typename T>
-__global__ __launch_bounds__(256) void diag_partial_kernel(DiagArgs<T> a, long long per_block) {
-  __shared__ double sh[10][256];
-  const Geo& g = a.g;
-  const long long ncell = (long long)g.n[0] * g.n[1] * g.n[2];
-  const long long c0 = (long long)blockIdx.x * per_block;
-  const long long c1 = min(ncell, c0 + per_block);
-  double acc[10];
-#pragma unroll
-  for (int q = 0; q < 10; ++q) acc[q] = 0.0;
-  for (long long cidx = c0 + threadIdx.x; cidx < c1; cidx += blockDim.x) {
-    const int i = (int)(cidx % g.n[0]);
-    const long long r = cidx / g.n[0];
-    const int j = (int)(r % g.n[1]);
-    const int k = (int)(r / g.n[1]);
-    const long long s = (long long)i * g.st[0] + (long long)j * g.st[1] + (long long)k * g.st[2];
-    // cell widths; on a uniform mesh the volume and face areas are applied
-    // once at the end, on an irregular one each cell and face carries its own
-    // (Sect. 2.5), and the final factors are 1
-    const bool nu = a.wid[0] != nullptr;
-    const double hx = nu ? (double)a.wid[0][i] : g.h[0];
-    const double hy = nu ? (double)a.wid[1][j] : g.h[1];
-    const double hz = nu ? (double)a.wid[2][k] : g.h[2];
-    const double cw = nu ? hx * hy * hz : 1.0;
-    const double ax = nu ? hy * hz : 1.0, ay = nu ? hx * hz : 1.0, az = nu ? hx * hy : 1.0;
-#pragma unroll
-    for (int f = 0; f < 5; ++f) acc[f] += (double)a.u[f][s] * cw;
-    const long long sx = s + (long long)(map_face(i + 1, g.n[0], g.bc[0]) - i) * g.st[0];
-    const long long sy = s + (long long)(map_face(j + 1, g.n[1], g.bc[1]) - j) * g.st[1];
-    const long long sz = s + (long long)(map_face(k + 1, g.n[2], g.bc[2]) - k) * g.st[2];
-    // Eq. (62), each difference over its cell's width
-    const double div = ((double)a.b[0][sx] - (double)a.b[0][s]) / hx +
-                       ((double)a.b[1][sy] - (double)a.b[1][s]) / hy +
-                       ((double)a.b[2][sz] - (double)a.b[2][s]) / hz;
-    acc[8] = fmax(acc[8], fabs(div));
-    // face sums over real faces: the low face of every cell, plus face n on
-    // outflow axes (owned by the last cell)
-    const double bx = (double)a.b[0][s], by = (double)a.b[1][s], bz = (double)a.b[2][s];
-    acc[5] += bx * ax;
-    acc[6] += by * ay;
-    acc[7] += bz * az;
-    acc[9] = fmax(acc[9], fmax(fabs(bx), fmax(fabs(by), fabs(bz))));
-    if (g.bc[0] == 1 && i == g.n[0] - 1) {
-      const double v = (double)a.b[0][sx];
-      acc[5] += v * ax;
-      acc[9] = fmax(acc[9], fabs(v));
-    }
-    if (g.bc[1] == 1 && j == g.n[1] - 1) {
-      const double v = (double)a.b[1][sy];
-      acc[6] += v * ay;
-      acc[9] = fmax(acc[9], fabs(v));
-    }
-    if (g.bc[2] == 1 && k == g.n[2] - 1) {
-      const double v = (double)a.b[2][sz];
-      acc[7] += v * az;
-      acc[9] = fmax(acc[9], fabs(v));
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 10; ++q) sh[q][threadIdx.x] = acc[q];
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-#pragma unroll
-      for (int q = 0; q < 10; ++q) {
-        if (q == 8 || q == 9)
-          sh[q][threadIdx.x] = fmax(sh[q][threadIdx.x], sh[q][threadIdx.x + w]);
-        else
-          sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
-      }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < 10) a.partial[(long long)blockIdx.x * 10 + threadIdx.x] = sh[threadIdx.x][0];
-}
-
-__global__ void diag_final_kernel(const double* partial, int nblocks, double* out, double vol, double ax, double ay,
-                                  double az) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double acc[10];
-  for (int q = 0; q < 10; ++q) acc[q] = 0.0;
-  for (int b = 0; b < nblocks; ++b)
-    for (int q = 0; q < 10; ++q) {
-      const double v = partial[(long long)b * 10 + q];
-      if (q == 8 || q == 9)
-        acc[q] = fmax(acc[q], v);
-      else
-        acc[q] += v;
-    }
-  for (int q = 0; q < 5; ++q) out[q] = acc[q] * vol;
-  out[5] = acc[5] * ax;
-  out[6] = acc[6] * ay;
-  out[7] = acc[7] * az;
-  out[8] = acc[8];
-  out[9] = acc[9];
-}
-
-// Self-test of the lane-shift primitive: out[64*it + lane] = the value of
-// lane - 1 of (100*it + lane), 0 in lane 0, over two iterations (128 entries).
-__global__ void lane_shift_selftest_kernel(float* out) {
-  const int lane = threadIdx.x & 63;
-  for (int it = 0; it < 2; ++it) {
-    const float cur = (float)(100 * it + lane);
-    out[64 * it + lane] = lane_shr(cur);
-  }
 }
 
 }  // namespace fish
