@@ -16,6 +16,8 @@
 
 namespace fish {
 
+struct SweepSel;
+
 struct DeviceBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
@@ -192,20 +194,11 @@ class Engine {
   int build_lists();
   template <typename T>
   int sub_operator(int op, int d);
+  SweepSel sweep_sel() const;               // the kernel selection of the sweeps
   template <typename T, int D>
   int fluid_dispatch();
-  template <typename T, int D, int LIM>
-  void fluid_dispatch_lim();
-  template <typename T, int D, int GRAV, bool HSE, int LIM, bool NU>
-  void launch_fluid();
-  template <typename T, int D, int GRAV, bool HSE, int LIM>
-  void launch_fluid_mesh();
   template <typename T, int D>
   int field_sweep();
-  template <typename T, int D, int LIM>
-  int field_sweep_lim();
-  template <typename T, int D, int LIM, bool NU>
-  void launch_field();
   template <typename T>
   int launch_check_cfl();
   template <typename T>

@@ -5,6 +5,7 @@
 #include "engine.h"
 
 #include "launch.h"
+#include "launch_api.h"
 #include "step_kernels.h"
 #include "sweeps.h"
 
@@ -634,6 +635,29 @@ static int single_box_target(const HostBox& b, int kind, int target, int groups)
   return target;
 }
 
+// Segments per pencil of a y/z kind, ceil(n_d / segment length); 0 for the
+// other kinds.
+static int kind_segments(const HostBox& b, int kind, int par) {
+  if (kind == K_FLUID_Y || kind == K_FIELD_Y) return (b.n[1] + par - 1) / par;
+  if (kind == K_FLUID_Z || kind == K_FIELD_Z) return (b.n[2] + par - 1) / par;
+  return 0;
+}
+
+void plan_single_box(const int n[3], const int bc[3], int par[K_NUM], int nseg[K_NUM], long long waves[K_NUM]) {
+  HostBox b;
+  for (int a = 0; a < 3; ++a) {
+    b.n[a] = n[a];
+    b.bc[a] = bc[a];
+    b.o[a] = bc[a] == 1 ? 1 : 0;
+  }
+  const Tuning t = default_tuning();
+  for (int k = 0; k < K_NUM; ++k) {
+    const int target = single_box_target(b, k, t.target[k], t.groups[k]);
+    waves[k] = kind_waves(b, k, target, t.groups[k], &par[k]);
+    nseg[k] = kind_segments(b, k, par[k]);
+  }
+}
+
 int Engine::build_lists() {
   std::vector<int> slots;
   for (int s = 0; s < (int)boxes.size(); ++s)
@@ -679,10 +703,7 @@ int Engine::build_lists() {
         return fail(5, "work list exceeds the launch size");
       d.wave0[k] = (int)list[k].size();
       d.par[k] = par;
-      if (k == K_FLUID_Y || k == K_FLUID_Z || k == K_FIELD_Y || k == K_FIELD_Z) {
-        const int ax = (k == K_FLUID_Y || k == K_FIELD_Y) ? 1 : 2;
-        d.nseg[k] = (b.n[ax] + par - 1) / par;
-      }
+      d.nseg[k] = kind_segments(b, k, par);
       list[k].insert(list[k].end(), (size_t)w, t);
     }
   }
@@ -1235,6 +1256,28 @@ done:
   // the timed sweeps left the CFL speeds of other states: reduce the current one again
   if (!rc && !rc2) rc2 = check_cfl_all();
   return rc ? rc : rc2;
+}
+
+// ------------------------------------------------------------ launches (launch_api.h)
+template <typename T>
+void launch_check(const CheckLaunch<T>& L, hipStream_t stream) {
+  if (L.wl.nwaves > 0)
+    hipLaunchKernelGGL((check_cfl_kernel<T>), dim3(grid_for((long long)L.wl.nwaves * 64)), dim3(kBlock), 0, stream, L);
+}
+template void launch_check<float>(const CheckLaunch<float>&, hipStream_t);
+template void launch_check<double>(const CheckLaunch<double>&, hipStream_t);
+
+void launch_reset_cmax(const BoxDesc* boxes, int nb, Scalars* sc, hipStream_t stream) {
+  hipLaunchKernelGGL(reset_cmax_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, stream, boxes, nb, sc);
+}
+void launch_finalize_dt(const BoxDesc* boxes, int nb, Scalars* sc, hipStream_t stream) {
+  hipLaunchKernelGGL(finalize_dt_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, stream, boxes, nb, sc);
+}
+void launch_set_dt(const BoxDesc* boxes, int nb, Scalars* sc, double dt, hipStream_t stream) {
+  hipLaunchKernelGGL(set_dt_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, stream, boxes, nb, sc, dt);
+}
+void launch_advance_time(const BoxDesc* boxes, int nb, Scalars* sc, hipStream_t stream) {
+  hipLaunchKernelGGL(advance_time_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, stream, boxes, nb, sc);
 }
 
 int selftest_lane_shift(int device, float* out128) {

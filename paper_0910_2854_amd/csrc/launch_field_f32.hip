@@ -3,6 +3,9 @@
 
 namespace fish {
 template int Engine::field_sweep<float, 0>();
+template void launch_field_sweep<float, 0>(const SweepSel&, const FieldLaunch<float>&);
 template int Engine::field_sweep<float, 1>();
+template void launch_field_sweep<float, 1>(const SweepSel&, const FieldLaunch<float>&);
 template int Engine::field_sweep<float, 2>();
+template void launch_field_sweep<float, 2>(const SweepSel&, const FieldLaunch<float>&);
 }  // namespace fish

@@ -3,6 +3,9 @@
 
 namespace fish {
 template int Engine::field_sweep<double, 0>();
+template void launch_field_sweep<double, 0>(const SweepSel&, const FieldLaunch<double>&);
 template int Engine::field_sweep<double, 1>();
+template void launch_field_sweep<double, 1>(const SweepSel&, const FieldLaunch<double>&);
 template int Engine::field_sweep<double, 2>();
+template void launch_field_sweep<double, 2>(const SweepSel&, const FieldLaunch<double>&);
 }  // namespace fish

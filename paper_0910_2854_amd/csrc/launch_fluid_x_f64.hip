@@ -3,4 +3,5 @@
 
 namespace fish {
 template int Engine::fluid_dispatch<double, 0>();
+template void launch_fluid_sweep<double, 0>(const SweepSel&, const FluidLaunch<double>&, bool);
 }  // namespace fish

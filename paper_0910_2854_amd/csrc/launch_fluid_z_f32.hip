@@ -3,4 +3,5 @@
 
 namespace fish {
 template int Engine::fluid_dispatch<float, 2>();
+template void launch_fluid_sweep<float, 2>(const SweepSel&, const FluidLaunch<float>&, bool);
 }  // namespace fish

@@ -3,4 +3,5 @@
 
 namespace fish {
 template int Engine::fluid_dispatch<double, 2>();
+template void launch_fluid_sweep<double, 2>(const SweepSel&, const FluidLaunch<double>&, bool);
 }  // namespace fish
