@@ -99,8 +99,8 @@ int fish_create(const fish_params* p, fish_ctx** out);
 void fish_destroy(fish_ctx* ctx);
 
 /* Message describing the last failure on ctx (never NULL).  With ctx NULL:
- * the message of the last fish_create or fish_batch_create that failed on
- * the calling thread (its context no longer exists). */
+ * the message of the last fish_create, fish_batch_create or
+ * fish_strang_step_noalloc that failed on the calling thread. */
 const char* fish_last_error(const fish_ctx* ctx);
 
 /* Upload a state (layouts above).  phi is required when gravity is on and
@@ -226,6 +226,63 @@ int fish_set_shape(fish_ctx* ctx, int kind, int32_t value);
  * x sweeps make their first lanes a halo, so nothing crosses iterations).
  * Synchronous; the caller owns out128. */
 int fish_selftest_lane_shift(int device, float* out128);
+
+/* ------------------------------------------------------------------------
+ * Allocation-free double step, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  The double step of fish_strang_step on one box whose
+ * state the caller keeps in device memory, with no context: the library
+ * allocates nothing, neither device nor pinned memory.
+ *
+ * Arrays (device memory of p->device, owned by the caller, storage precision
+ * of p->precision: double for FISH_FP64, float for FISH_FP32):
+ *   state[8] : rho, m_x, m_y, m_z, E, b_x, b_y, b_z, each of
+ *              (nx+ox)(ny+oy)(nz+oz) elements, o_d = 1 on an outflow axis
+ *              and 0 on a periodic one; entry (i, j, k) at
+ *              i + (nx+ox) (j + (ny+oy) k).  Cell arrays hold cell (i, j, k)
+ *              for i < nx, j < ny, k < nz; b_x holds face i (between cells
+ *              i-1 and i) for i < nx+ox, and likewise b_y along y and b_z
+ *              along z (on a periodic axis face n is face 0 and is not
+ *              stored).  Entries outside these ranges are not read.
+ *              Read and overwritten with the state after the step.
+ *   work[8]  : eight more arrays of the same size, distinct from state;
+ *              overwritten (the sub-operators alternate between the two sets,
+ *              an even number of times per field).
+ *   phi      : with gravity, the potential in the cell layout; else ignored.
+ * dt > 0 is used as given; dt == 0 takes the CFL step of the state (Eq. 14),
+ * computed on the device.  report: NULL, or device memory for one
+ * fish_step_report, written after the step.  p->alloc and p->free are
+ * ignored; p->stream is the stream the work is enqueued on (NULL = default).
+ * Asynchronous.  Irregular meshes are not available here.
+ *
+ * Scratch: the step's box table, step scalars and work lists live in one
+ * static device array of FISH_NOALLOC_SCRATCH_BYTES on each GPU the call
+ * runs on, held until the process ends and found at the first call on that
+ * GPU.  Every call on a GPU uses the same array, and each call rewrites what
+ * it reads: calls in stream order are independent, calls that overlap on one
+ * GPU (two host threads, two streams) race and give wrong results.  A box
+ * that needs more than FISH_NOALLOC_MAX_WAVES wavefronts in one sweep is
+ * refused (FISH_ERR_UNSUPPORTED): every box up to 1024^3 cells fits, a flat
+ * box such as 16384 x 1 x 16384 does not.
+ *
+ * Returns FISH_ERR_ARG for an invalid setting, a null or repeated array, or
+ * a missing phi; FISH_ERR_UNSUPPORTED beyond the limits (also an array of
+ * 4 GiB or more); FISH_ERR_DEVICE when a HIP call or launch fails.  The
+ * message is fish_last_error(NULL).  A bad state (rho <= 0, p <= 0 or a
+ * non-finite value, before or after the step) is reported in the report,
+ * not by the return value.  The caller's current device is restored. */
+#define FISH_NOALLOC_MAX_WAVES (1 << 20)
+#define FISH_NOALLOC_SCRATCH_BYTES (2048 + 4 * FISH_NOALLOC_MAX_WAVES)
+
+typedef struct fish_step_report {
+  double dt;       /* the step size of every sub-operator (0 for a state refused before the step) */
+  double dt_next;  /* CFL step of the new state, Eq. (14) (0 when it is bad)                      */
+  int32_t status;  /* FISH_OK, or FISH_ERR_STATE for a bad state before or after the step          */
+  int32_t pad;
+} fish_step_report;
+
+int fish_strang_step_noalloc(const fish_params* p, void* const state[8], void* const work[8], const void* phi,
+                             double dt, fish_step_report* report);
 
 /* ------------------------------------------------------------------------
  * Batches: many independent boxes of different shapes advanced together.

@@ -46,6 +46,15 @@ class Params(ctypes.Structure):
     ]
 
 
+class StepReport(ctypes.Structure):
+    """fish_step_report: what fish_strang_step_noalloc writes to device memory."""
+    _fields_ = [("dt", ctypes.c_double), ("dt_next", ctypes.c_double),
+                ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+NOALLOC_MAX_WAVES = 1 << 20
+
+
 class FishError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"fish error {code}: {msg}")
@@ -100,7 +109,7 @@ EXPORTS = ("fish_create", "fish_destroy", "fish_last_error", "fish_set_state", "
            "fish_batch_use_graph", "fish_batch_autotune", "fish_batch_sync", "fish_batch_timing_enable",
            "fish_batch_timing_read", "fish_set_shape", "fish_batch_set_shape", "fish_server_create", "fish_server_destroy", "fish_server_last_error",
            "fish_server_batch", "fish_server_submit", "fish_server_pump", "fish_server_stats", "fish_set_spacing",
-           "fish_advance_to", "fish_batch_set_spacing")
+           "fish_advance_to", "fish_batch_set_spacing", "fish_strang_step_noalloc")
 KERNEL_FLUID, KERNEL_FIELD, KERNEL_CHECK = 1, 2, 8
 KINDS = ("fluid_x", "fluid_y", "fluid_z", "field_x", "field_y", "field_z", "check")
 
@@ -200,6 +209,8 @@ def load_library(path: str = LIB_PATH):
     lib.fish_set_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int32]
     lib.fish_set_spacing.argtypes = [vp, ctypes.c_int, P(ctypes.c_double)]
     lib.fish_advance_to.argtypes = [vp, d, ctypes.c_int, P(ctypes.c_int), P(d)]
+    lib.fish_strang_step_noalloc.argtypes = [P(Params), P(vp), P(vp), vp, d, vp]
+    lib.fish_strang_step_noalloc.restype = ctypes.c_int
     lib.fish_set_spacing.restype = ctypes.c_int
     lib.fish_batch_set_spacing.argtypes = [vp, ctypes.c_int, ctypes.c_int, P(ctypes.c_double)]
     lib.fish_batch_set_spacing.restype = ctypes.c_int
@@ -227,6 +238,77 @@ def load_library(path: str = LIB_PATH):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def storage_shape(n, bc):
+    """(nz+oz, ny+oy, nx+ox): the shape of every array of a box in the storage
+    layout (o_d = 1 on an outflow axis, 0 on a periodic one)."""
+    nx, ny, nz = n
+    return (nz + int(bc[2] == OUTFLOW), ny + int(bc[1] == OUTFLOW), nx + int(bc[0] == OUTFLOW))
+
+
+def to_storage(st, n, bc, dtype):
+    """The eight arrays rho, m_x, m_y, m_z, E, b_x, b_y, b_z (and phi, or
+    None) of a state in the interface layout, in the storage layout and
+    precision of fish_strang_step_noalloc (zeros outside each array's
+    extent; face n of a periodic axis dropped)."""
+    nx, ny, nz = n
+    ox, oy, oz = (int(b == OUTFLOW) for b in bc)
+    shape = storage_shape(n, bc)
+    out = []
+    for k in range(5):
+        a = np.zeros(shape, dtype=dtype)
+        a[:nz, :ny, :nx] = st["cell"][k]
+        out.append(a)
+    a = np.zeros(shape, dtype=dtype)
+    a[:nz, :ny, :nx + ox] = st["bx"][:, :, :nx + ox]
+    out.append(a)
+    a = np.zeros(shape, dtype=dtype)
+    a[:nz, :ny + oy, :nx] = st["by"][:, :ny + oy, :]
+    out.append(a)
+    a = np.zeros(shape, dtype=dtype)
+    a[:nz + oz, :ny, :nx] = st["bz"][:nz + oz]
+    out.append(a)
+    phi = None
+    if st.get("phi") is not None:
+        phi = np.zeros(shape, dtype=dtype)
+        phi[:nz, :ny, :nx] = st["phi"]
+    return out, phi
+
+
+def from_storage(arrays, n, bc):
+    """The state (interface layout, FP64) of eight storage-layout arrays; on
+    a periodic axis face n is written equal to face 0."""
+    nx, ny, nz = n
+    ox, oy, oz = (int(b == OUTFLOW) for b in bc)
+    a = [np.asarray(x, dtype=np.float64) for x in arrays]
+    cell = np.stack([a[k][:nz, :ny, :nx] for k in range(5)])
+    bx = a[5][:nz, :ny, :nx + ox]
+    by = a[6][:nz, :ny + oy, :nx]
+    bz = a[7][:nz + oz, :ny, :nx]
+    if not ox:
+        bx = np.concatenate([bx, bx[:, :, :1]], axis=2)
+    if not oy:
+        by = np.concatenate([by, by[:, :1, :]], axis=1)
+    if not oz:
+        bz = np.concatenate([bz, bz[:1]], axis=0)
+    return {"cell": np.ascontiguousarray(cell), "bx": np.ascontiguousarray(bx), "by": np.ascontiguousarray(by),
+            "bz": np.ascontiguousarray(bz)}
+
+
+def strang_step_noalloc(params, state, work, phi=None, dt=0.0, report=None):
+    """fish_strang_step_noalloc: one double step on device arrays in the
+    storage layout (params: a Params; state, work: 8 device addresses each;
+    phi: a device address or None; report: the device address of a
+    StepReport, or None).  Enqueued on params.stream; raises FishError."""
+    lib = load_library()
+    vp = ctypes.c_void_p
+    st = (vp * 8)(*[int(a) for a in state])
+    wk = (vp * 8)(*[int(a) for a in work])
+    rc = lib.fish_strang_step_noalloc(ctypes.byref(params), st, wk, vp(int(phi)) if phi else None, float(dt),
+                                      vp(int(report)) if report else None)
+    if rc != FISH_OK:
+        raise FishError(rc, lib.fish_last_error(None).decode())
 
 
 def selftest_lane_shift(device=0):
@@ -267,6 +349,27 @@ class _TorchAllocator:
         self.free = _FREE(free)
 
 
+def make_params(nx, ny, nz, dx=None, dy=None, dz=None, gamma=5.0 / 3.0, cfl=0.5, limiter=VANLEER,
+                predictor_alpha=1.0, bc=(PERIODIC,) * 3, precision="fp64", gravity=False, hse=False, device=0,
+                stream=None):
+    """A fish_params (spacing 1/n per axis unless given; no allocator)."""
+    p = Params()
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    p.dx = 1.0 / nx if dx is None else float(dx)
+    p.dy = 1.0 / ny if dy is None else float(dy)
+    p.dz = 1.0 / nz if dz is None else float(dz)
+    p.gamma, p.cfl = float(gamma), float(cfl)
+    p.limiter = int(limiter)
+    p.predictor_alpha = float(predictor_alpha)
+    for a in range(3):
+        p.bc[a] = int(bc[a])
+    p.precision = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
+    p.gravity, p.hse = gravity_mode(gravity), int(bool(hse))
+    p.device = int(device)
+    p.stream = ctypes.c_void_p(int(stream)) if stream else None
+    return p
+
+
 class Box:
     """One box advanced by the HIP library on one GPU stream."""
 
@@ -276,19 +379,8 @@ class Box:
         lib = load_library()
         self._lib = lib
         self.shape = (int(nz), int(ny), int(nx))
-        p = Params()
-        p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
-        p.dx = 1.0 / nx if dx is None else float(dx)
-        p.dy = 1.0 / ny if dy is None else float(dy)
-        p.dz = 1.0 / nz if dz is None else float(dz)
-        p.gamma, p.cfl = float(gamma), float(cfl)
-        p.limiter = int(limiter)
-        p.predictor_alpha = float(predictor_alpha)
-        for a in range(3):
-            p.bc[a] = int(bc[a])
-        p.precision = {"fp64": FP64, "fp32": FP32}[precision] if isinstance(precision, str) else int(precision)
-        p.gravity, p.hse = gravity_mode(gravity), int(bool(hse))
-        p.device = int(device)
+        p = make_params(nx, ny, nz, dx, dy, dz, gamma, cfl, limiter, predictor_alpha, bc, precision, gravity, hse,
+                        device)
         self._allocator = None
         if stream is None or use_torch_allocator:
             import torch

@@ -16,8 +16,11 @@
 
 #include "../../include/fish.h"
 #include "batch.h"
+#include "capi.h"
 #include "engine.h"
 
+using fish::check_common;
+using fish::check_runtime;
 using fish::Engine;
 using fish::EngineConfig;
 using fish::Scalars;
@@ -29,7 +32,7 @@ struct fish_ctx {
 };
 
 
-namespace {
+namespace fish {
 
 int check_common(double gamma, int limiter, double alpha, int precision, int gravity, int hse) {
   if (!(gamma > 1.0) || !std::isfinite(gamma)) return FISH_ERR_ARG;
@@ -40,6 +43,10 @@ int check_common(double gamma, int limiter, double alpha, int precision, int gra
   if (hse && !gravity) return FISH_ERR_ARG;
   return FISH_OK;
 }
+
+}  // namespace fish
+
+namespace {
 
 double cmax_of(const Scalars& s) {
   double v;
@@ -79,11 +86,16 @@ int collect_runtime(struct dl_phdr_info* info, size_t, void* data) {
   return 0;
 }
 
-// 0 when the caller's stream or allocator can belong to this library's
-// runtime; FISH_ERR_DEVICE with a message when another HIP runtime is loaded
-// in the process and the caller passes either (checked before any HIP call).
-int check_runtime(const void* stream, bool has_alloc, std::string* msg) {
-  if (!stream && !has_alloc) return FISH_OK;  // everything is made by this library's runtime
+}  // namespace
+
+namespace fish {
+
+void set_thread_error(const std::string& msg) { g_create_err = msg; }
+
+// Checked before any HIP call; streams, allocators and device memory of the
+// caller are all made by the runtime that made them.
+int check_runtime(const void* stream, bool caller_memory, std::string* msg) {
+  if (!stream && !caller_memory) return FISH_OK;  // everything is made by this library's runtime
   std::vector<std::string> loaded;
   dl_iterate_phdr(collect_runtime, &loaded);
   if (loaded.size() <= 1) return FISH_OK;
@@ -98,7 +110,8 @@ int check_runtime(const void* stream, bool has_alloc, std::string* msg) {
          "that owns them (with PyTorch: import torch first), or pass stream = NULL and alloc = NULL";
   return FISH_ERR_DEVICE;
 }
-}  // namespace
+
+}  // namespace fish
 
 extern "C" {
 

@@ -129,3 +129,63 @@ def test_the_binding_maps_one_hip_runtime():
     runtime: one copy of libamdhip64 in the process."""
     fish.load_library()
     assert len(fish.hip_runtimes_loaded()) == 1
+
+
+def _fake_arrays(base):
+    # addresses that are never dereferenced: every call below is refused by
+    # the host checks before any HIP call
+    return [base + 0x1000 * i for i in range(8)]
+
+
+def test_noalloc_step_refuses_bad_calls_without_touching_a_device():
+    lib = fish.load_library()
+    vp = ctypes.c_void_p
+    ok = _valid_params((8, 8, 8), fish.FP64)
+    st, wk = (vp * 8)(*_fake_arrays(0x100000)), (vp * 8)(*_fake_arrays(0x900000))
+    # a null array, a repeated array, no phi with gravity, a negative dt, a bad setting
+    holes = (vp * 8)(*(_fake_arrays(0x100000)[:7] + [0]))
+    assert lib.fish_strang_step_noalloc(ctypes.byref(ok), holes, wk, None, 0.0, None) == fish.FISH_ERR_ARG
+    assert lib.fish_strang_step_noalloc(ctypes.byref(ok), st, st, None, 0.0, None) == fish.FISH_ERR_ARG
+    assert lib.fish_strang_step_noalloc(None, st, wk, None, 0.0, None) == fish.FISH_ERR_ARG
+    assert lib.fish_strang_step_noalloc(ctypes.byref(ok), st, wk, None, -1.0, None) == fish.FISH_ERR_ARG
+    grav = _valid_params((8, 8, 8), fish.FP64)
+    grav.gravity = 1
+    assert lib.fish_strang_step_noalloc(ctypes.byref(grav), st, wk, None, 0.0, None) == fish.FISH_ERR_ARG
+    bad = _valid_params((8, 8, 8), fish.FP64)
+    bad.gamma = 1.0
+    assert lib.fish_strang_step_noalloc(ctypes.byref(bad), st, wk, None, 0.0, None) == fish.FISH_ERR_ARG
+    assert b"dt" in lib.fish_last_error(None) or b"invalid" in lib.fish_last_error(None)
+
+
+def test_noalloc_step_refuses_a_box_beyond_its_scratch():
+    """The scratch holds 2^20 work-list entries: a 16384 x 1 x 16384 FP32 box
+    (1 GiB per array, accepted by fish_create) needs 2^22 wavefronts in its y
+    sweep and is refused before any HIP call; 1024^3 FP32 (every wave count at
+    most 2^20) is refused only for its 4 GiB arrays."""
+    lib = fish.load_library()
+    vp = ctypes.c_void_p
+    st, wk = (vp * 8)(*_fake_arrays(0x100000)), (vp * 8)(*_fake_arrays(0x900000))
+    flat = _valid_params((16384, 1, 16384), fish.FP32)
+    assert lib.fish_strang_step_noalloc(ctypes.byref(flat), st, wk, None, 0.0, None) == fish.FISH_ERR_UNSUPPORTED
+    msg = lib.fish_last_error(None).decode()
+    assert "4194304 wavefronts" in msg and str(fish.NOALLOC_MAX_WAVES) in msg, msg
+    big = _valid_params((1024, 1024, 1024), fish.FP32)
+    assert lib.fish_strang_step_noalloc(ctypes.byref(big), st, wk, None, 0.0, None) == fish.FISH_ERR_UNSUPPORTED
+    assert "4 GiB" in lib.fish_last_error(None).decode()
+
+
+def test_storage_layout_round_trip():
+    """to_storage / from_storage: the interface arrays come back unchanged
+    (face n of a periodic axis is face 0), every other entry is zero."""
+    import numpy as np
+    import fish_inputs as fi
+    n, bc = (7, 5, 6), (fish.PERIODIC, fish.OUTFLOW, fish.PERIODIC)
+    st = fi.random_fourier_state(n, seed=3, mach=0.8, beta=2.0, kmax=2)
+    arrays, phi = fish.to_storage(st, n, bc, np.float64)
+    assert phi is None
+    assert all(a.shape == fish.storage_shape(n, bc) == (6, 6, 7) for a in arrays)
+    back = fish.from_storage(arrays, n, bc)
+    for k in ("cell", "bx", "by", "bz"):
+        np.testing.assert_array_equal(back[k], st[k])
+    assert not arrays[0][:, 5, :].any()  # the outflow layer of a cell array
+    assert arrays[6][:, 5, :].any()      # face n of b_y on the outflow axis
