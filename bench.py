@@ -83,7 +83,8 @@ def stretched_widths(n, amp, phase):
     return w / w.sum()
 
 
-def run_gpu(fish, torch, st, n, precision, steps, warmup, cfl, segment, autotune=True, limiter=1, stretch=0.0):
+def run_gpu(fish, torch, st, n, precision, steps, warmup, cfl, segment, autotune=True, limiter=1, stretch=0.0,
+            x_strided=0):
     """Time `steps` Strang steps (dt from the device CFL step) in segments of at
     most `segment` steps, each started from the initial state: the state is
     re-uploaded and synchronised before a segment's clock starts and checked
@@ -100,6 +101,11 @@ def run_gpu(fish, torch, st, n, precision, steps, warmup, cfl, segment, autotune
             box.set_spacing(a, stretched_widths(n[a], stretch, float(a)))
     box.set_state(st)
     tuned = box.autotune(reps=5) if autotune else None
+    if x_strided:
+        # the measured alternative to the lanes policy for the x fluid sweep
+        box.set_shape("fluid_x", x_strided, 1, 1)
+        if tuned:
+            tuned["fluid_x"] = {"target": x_strided, "xcd_remap": 1, "alt_layout": 1}
     for _ in range(warmup):
         box.strang_step(0.0)
     torch.cuda.synchronize()
@@ -283,6 +289,15 @@ def bench_batch(args, torch, fish, fi):
     log(f"  graph: {wall_g * 1e3 / args.steps:.3f} ms/step, {valid_updates / wall_g:.3e} valid cell-updates/s")
     wall_e, ms_e = timed(False, args.steps, 0)
     log(f"  eager: {wall_e * 1e3 / args.steps:.3f} ms/step")
+    # the fluid sweep's launch time: further eager steps with a hipEvent around
+    # every fluid launch (kept out of the timed steps: the records add gaps)
+    hooked = max(2, args.steps // 10)
+    b.timing_enable(fish.KERNEL_FLUID, 8 * hooked)
+    b.step(hooked)
+    b.sync()
+    launches, fluid_ms = b.timing_read()
+    b.timing_enable(0)
+    fluid_avg_s = fluid_ms / max(1, launches) * 1e-3
     valid = sum(0 if b.info(i)["bad"] else 1 for i in ids)
     valid_cells = sum(j["n"][0] ** 3 for j, i in zip(jobs, ids) if not b.info(i)["bad"])
     b.close()
@@ -297,7 +312,7 @@ def bench_batch(args, torch, fish, fi):
             sample.append(j)
     sc = 0
     st_time = 0.0
-    for job, st in _gen_states(fi, sample, args.workers):
+    for job, st in _gen_states(fi, sample, args.workers) if sample else ():
         g = fish.Box(*job["n"], precision="fp32")
         g.set_state(st)
         g.strang_step(0.0)
@@ -309,9 +324,11 @@ def bench_batch(args, torch, fish, fi):
         st_time += time.perf_counter() - t0
         sc += job["n"][0] ** 3 * args.steps
         g.close()
-    single_rate = sc / st_time
+    single_rate = sc / st_time if st_time else None
     value = valid_updates / wall_g
     raw = cells * args.steps / wall_g
+    bytes_fluid = cells * 13 * 4
+    traffic, _ = load_counters("fluid_sweep_traffic_batch.json", 4, cells)
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall_g * 1e3 / args.steps, "higher_is_better": True,
@@ -325,12 +342,19 @@ def bench_batch(args, torch, fish, fi):
         "latency_ms": {"p50": pct(ms_g, 50), "p99": pct(ms_g, 99)},
         "step_roofline": {"bytes_per_cell": 384, "achieved_GBs": value * 384 / 1e9, "peak_GBs": HBM_PEAK_GBS,
                           "frac": value * 384 / 1e9 / HBM_PEAK_GBS},
+        "roofline": {"bound": "hbm", "achieved": bytes_fluid / fluid_avg_s / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": bytes_fluid / fluid_avg_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "fluid sweep class over the whole batch (fluid_lanes_kernel, fluid_strided_kernel), "
+                               "every box in each launch",
+                     "avg_launch_ms": fluid_avg_s * 1e3, "launches": launches,
+                     "timed_with": f"{hooked} further eager double steps with a hipEvent around every fluid launch",
+                     "algorithmic_bytes_per_launch": bytes_fluid},
         "all_boxes_rate": {"value": raw, "note": "every box's cells times every timed step, including boxes that "
                                                  "stopped on a bad state (their launches still run)"},
         "eager": {"value": cells * args.steps / wall_e, "ms_per_step": wall_e * 1e3 / args.steps},
         "single_box_path": {"value": single_rate, "boxes_sampled": len(sample),
                             "note": "same boxes, one single-box context each, stepped one box at a time"},
-        "speedup_vs_single_box": raw / single_rate,
+        "speedup_vs_single_box": raw / single_rate if single_rate else None,
         "boxes_valid_at_end": valid,
         "valid_cell_fraction": valid_cells / cells,
         "valid_work_fraction": valid_updates / (cells * args.steps),
@@ -519,6 +543,9 @@ def bench_sphere(args, torch, fish, fi):
     value = ncell * args.steps / wall
     fluid_avg_s = fluid_ms / max(1, launches) * 1e-3
     bytes_fluid = ncell * 14 * 4  # the fluid sweep also reads phi
+    # the counters were taken on the unsplit-gravity kernels at 512^3
+    traffic = (load_counters("fluid_sweep_traffic_512_sphere.json", 4, ncell)[0] if args.gravity == "unsplit"
+               else None)
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
@@ -530,7 +557,7 @@ def bench_sphere(args, torch, fish, fi):
         "step_roofline": {"bytes_per_cell": 408, "achieved_GBs": value * 408 / 1e9, "peak_GBs": HBM_PEAK_GBS,
                           "frac": value * 408 / 1e9 / HBM_PEAK_GBS},
         "roofline": {"bound": "hbm", "achieved": bytes_fluid / fluid_avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": bytes_fluid / fluid_avg_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "frac": bytes_fluid / fluid_avg_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "fluid sweep class with gravity + HSE (fluid_lanes_kernel, fluid_strided_kernel)",
                      "avg_launch_ms": fluid_avg_s * 1e3, "launches": launches,
                      "timed_with": f"{hooked} further double steps with a hipEvent around every fluid launch",
@@ -631,6 +658,220 @@ def bench_problems(args, torch, fish, fi):
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------ counter summaries
+# The rocprofv3 counter passes each workload's committed summary comes from
+# (REPO = the repository root on the GPU host; each pass is its own run).
+PMC_PASSES = (
+    ("rd", "TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum TCC_EA0_RDREQ_sum"),
+    ("wr", "TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum TCC_HIT_sum TCC_MISS_sum"),
+    ("sq1", "SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_SALU SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES "
+            "SQ_ACTIVE_INST_VALU GRBM_GUI_ACTIVE"),
+    ("sq2", "SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY SQ_INST_CYCLES_VMEM_RD SQ_THREAD_CYCLES_VALU SQ_INSTS_VALU_TRANS_F32 "
+            "SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_FMA_F32 SQ_INSTS_VALU_MUL_F32 GRBM_GUI_ACTIVE"),
+)
+PROFILED = {
+    # workload: (summary tag, bench arguments of the profiled run, description, fluid bytes per cell)
+    "box": ("256", "--no-cpu --no-fp64 --steps 2 --warmup 0 --segment 2",
+            "256^3 FP32 random-Fourier box (Mach 1, beta 1, |k|<=16), van Leer, autotuned shapes", 13 * 4),
+    "sphere": ("512_sphere", "--workload sphere --no-cpu --steps 2 --warmup 0",
+               "512^3 FP32 stratified sphere, outflow, unsplit gravity + HSE, default shapes", 14 * 4),
+    "batch": ("batch", "--workload batch --no-cpu --steps 2 --warmup 0 --single-sample 0",
+              "batch of 2048 FP32 boxes (edges 16-64), autotuned shapes, the eager double steps", 13 * 4),
+}
+COPY_PROBE = "--copy-probe 1024"
+TRACED = {
+    # tag: (bench arguments of the traced run, description, double steps summarised, later steps skipped)
+    "256": ("--no-cpu --no-fp64 --steps 5 --warmup 1 --segment 5",
+            "256^3 periodic random-Fourier box (Mach 1, beta 1, |k|<=16), van Leer, CFL 0.5, FP32 with FP64 pressure "
+            "recovery, autotuned work shapes; the 5 headline double steps (the bench then repeats them with its "
+            "launch-timing hook, which is not in these figures)", 5, 5),
+    "256_fp64": ("--no-cpu --steps 5 --warmup 1 --segment 5",
+                 "the same box in FP64 (the second half of the same run), autotuned work shapes; its 5 headline double "
+                 "steps", 5, 5),
+    "256_x_strided": ("--no-cpu --no-fp64 --steps 5 --warmup 1 --segment 5 --x-strided 128",
+                      "the same FP32 box with the x fluid sweep on the strided policy (lanes along y, segments of 128, "
+                      "XCD-grouped blocks) instead of the lanes policy, the CFL speed then from the check kernel; the "
+                      "5 headline double steps", 5, 5),
+    "512_sphere": ("--workload sphere --no-cpu --steps 5 --warmup 1",
+                   "512^3 stratified sphere, outflow, unsplit gravity + HSE, FP32 with FP64 pressure recovery, default "
+                   "shapes; the 5 headline double steps (2 hooked steps follow)", 5, 2),
+    "batch": ("--workload batch --no-cpu --steps 5 --warmup 1 --single-sample 0",
+              "batch of 2048 periodic FP32 boxes (edges 16-64), autotuned shapes; the 5 timed double steps, replays "
+              "of the captured graph (5 eager steps follow)", 5, 5),
+}
+
+
+def _pmc_dispatches(path, nsteps):
+    """Counter values per dispatch of the last nsteps double steps (from the
+    nsteps-th last begin_step_kernel on) of one rocprofv3 --pmc csv."""
+    import csv
+    import collections
+
+    disp = collections.OrderedDict()
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            d = disp.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"], "c": {},
+                                                        "t": (int(r["Start_Timestamp"]), int(r["End_Timestamp"]))})
+            d["c"][r["Counter_Name"]] = float(r["Counter_Value"])
+    ids = sorted(disp)
+    starts = [i for i in ids if "begin_step_kernel" in disp[i]["name"]]
+    return [disp[i] for i in ids if i >= starts[-nsteps]]
+
+
+def _fetch_bytes(a):
+    return 32 * a.get("TCC_EA0_RDREQ_32B_sum", 0) + 64 * a.get("TCC_EA0_RDREQ_64B_sum", 0) + \
+        128 * a.get("TCC_EA0_RDREQ_128B_sum", 0)
+
+
+def _write_bytes(a):
+    return 64 * a.get("TCC_EA0_WRREQ_64B_sum", 0) + 32 * (a.get("TCC_EA0_WRREQ_sum", 0) -
+                                                           a.get("TCC_EA0_WRREQ_64B_sum", 0))
+
+
+def summarize_counters(workload, outdir, cells, nsteps=2):
+    """Write profiles/fluid_sweep_traffic_<tag>.json and profiles/counters_<tag>.txt
+    from the counter passes of PMC_PASSES in outdir/pmc_<tag>_<pass> (and the
+    copy probe in outdir/pmccopy_rd, outdir/pmccopy_wr when present).  HBM
+    bytes are the L2's read and write requests weighted by their size."""
+    import collections
+
+    tag, bargs, desc, fluid_bpc = PROFILED[workload]
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    cnt = collections.Counter()
+    dur = collections.defaultdict(float)
+    for sub, _ in PMC_PASSES:
+        path = os.path.join(outdir, f"pmc_{tag}_{sub}", "run_counter_collection.csv")
+        if not os.path.exists(path):
+            continue
+        for d in _pmc_dispatches(path, nsteps):
+            n = d["name"].split("(")[0].replace("void ", "")
+            if sub == "rd":
+                cnt[n] += 1
+            if sub == "sq1":
+                dur[n] += (d["t"][1] - d["t"][0]) / 1e3
+            for k, v in d["c"].items():
+                agg[n][k] += v
+    calib = None
+    crd, cwr = os.path.join(outdir, "pmccopy_rd", "run_counter_collection.csv"), \
+        os.path.join(outdir, "pmccopy_wr", "run_counter_collection.csv")
+    if os.path.exists(crd) and os.path.exists(cwr):
+        import csv
+
+        c = collections.defaultdict(float)
+        for path in (crd, cwr):
+            with open(path) as f:
+                for r in csv.DictReader(f):
+                    if "copyBuffer" in r["Kernel_Name"]:
+                        c[r["Counter_Name"]] += float(r["Counter_Value"])
+        calib = {"probe": f"bench.py {COPY_PROBE}: three 1 GiB device-to-device copies",
+                 "read_GiB_per_copy": _fetch_bytes(c) / 3 / 2 ** 30, "write_GiB_per_copy": _write_bytes(c) / 3 / 2 ** 30}
+    cmds = ["cd /tmp && export TMPDIR=/tmp"] + [
+        f"rocprofv3 --pmc {c} --output-format csv -d $REPO/gpurun_out/pmc_{tag}_{sub} -o run -- "
+        f"python3 $REPO/bench.py {bargs}" for sub, c in PMC_PASSES] + [
+        f"rocprofv3 --pmc {PMC_PASSES[i][1]} --output-format csv -d $REPO/gpurun_out/pmccopy_{PMC_PASSES[i][0]} -o run "
+        f"-- python3 $REPO/bench.py {COPY_PROBE}" for i in (0, 1)] + [
+        f"python3 $REPO/bench.py --summarize {workload} --counters-dir $REPO/gpurun_out"]
+    fluid = [n for n in cnt if "fluid_" in n]
+    nl = sum(cnt[n] for n in fluid)
+    tot_f = sum(_fetch_bytes(agg[n]) for n in fluid)
+    tot_w = sum(_write_bytes(agg[n]) for n in fluid)
+    algo = fluid_bpc * cells
+    rec = {
+        "kernel": f"fluid sweep class, {desc}: the launches of the last {nsteps} double steps of the profiled run",
+        "kernel_hash": kernel_source_hash(), "cells": cells, "esize": 4,
+        "bytes_per_launch": (tot_f + tot_w) / nl, "fetch_bytes_per_launch": tot_f / nl,
+        "write_bytes_per_launch": tot_w / nl, "algorithmic_bytes_per_launch": algo,
+        "traffic_over_algorithmic": (tot_f + tot_w) / nl / algo,
+        "byte_counts": "HBM reads as the L2's read requests by size (32 x TCC_EA0_RDREQ_32B + 64 x TCC_EA0_RDREQ_64B "
+                       "+ 128 x TCC_EA0_RDREQ_128B), writes as 64 x TCC_EA0_WRREQ_64B + 32 x the other write "
+                       "requests; no calibration factor (the copy probe checks the counting)",
+        "calibration_check": calib, "launches": nl,
+        "per_kernel": [{"kernel": n, "dispatches": cnt[n], "fetch_bytes": _fetch_bytes(agg[n]) / cnt[n],
+                        "write_bytes": _write_bytes(agg[n]) / cnt[n]} for n in fluid],
+        "commands": cmds,
+        "valu_wave_insts_per_launch": (sum(agg[n].get("SQ_INSTS_VALU", 0) for n in fluid) / nl) or None,
+    }
+    with open(os.path.join(ROOT, "profiles", f"fluid_sweep_traffic_{tag}.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    lines = [f"Counters per launch of every sweep kernel: {desc}; the last {nsteps} double steps of each counter run",
+             "(dispatches from the matching begin_step_kernel on).  HBM bytes from the L2's read and write requests",
+             "by size" + (f" (a 1 GiB device copy reads {calib['read_GiB_per_copy']:.3f} GiB and writes "
+                          f"{calib['write_GiB_per_copy']:.3f} GiB per copy in the same counting)" if calib else "") +
+             ".  VALU busy: the kernel's VALU wave-instructions at one per 4 cycles per SIMD (1024 SIMDs, 2.4 GHz)",
+             "over its duration in the sq1 pass.", "", "commands (REPO = the repository root on the GPU host):"] + \
+        ["  " + c for c in cmds] + ["", f"{'kernel':58s} {'n':>3s} {'dur us':>7s} {'fetch MB':>9s} {'write MB':>9s} "
+                                        f"{'algo MB':>8s} {'x algo':>6s} {'TB/s':>5s} {'VALU/cell':>9s} "
+                                        f"{'INT32/cell':>10s} {'VALU busy':>9s}"]
+    for n in sorted(cnt, key=lambda n: -agg[n].get("SQ_INSTS_VALU", 0)):
+        kind = "fluid" if "fluid_" in n else ("field" if "field_" in n else ("check" if "check_" in n else None))
+        if kind is None:
+            continue
+        a, k = agg[n], cnt[n]
+        d = dur[n] / k if dur[n] else 0.0
+        f, w = _fetch_bytes(a) / k, _write_bytes(a) / k
+        al = {"fluid": fluid_bpc, "field": 8 * 4, "check": 8 * 4}[kind] * cells
+        valu = a.get("SQ_INSTS_VALU", 0)
+        lines.append(f"{n.replace('fish::', '')[:58]:58s} {k:3d} {d:7.1f} {f / 1e6:9.1f} {w / 1e6:9.1f} {al / 1e6:8.1f} "
+                     f"{(f + w) / al:6.2f} {((f + w) / d / 1e6) if d else 0:5.2f} {valu * 64 / k / cells:9.1f} "
+                     f"{a.get('SQ_INSTS_VALU_INT32', 0) * 64 / k / cells:10.1f} "
+                     f"{(valu / k * 4 / 1024 / (d * 1e-6 * 2.4e9)) if d else 0:9.2f}")
+    with open(os.path.join(ROOT, "profiles", f"counters_{tag}.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines[-12:]))
+    print(json.dumps({k: rec[k] for k in ("bytes_per_launch", "traffic_over_algorithmic", "launches")}))
+
+
+def summarize_trace(tag, outdir):
+    """Write profiles/kernels_<tag>.txt from the rocprofv3 kernel trace in
+    outdir/pk_<tag>: per kernel the calls, average, minimum and maximum
+    duration over the summarised double steps."""
+    import csv
+    import collections
+
+    bargs, desc, nsteps, skip = TRACED[tag]
+    with open(os.path.join(outdir, f"pk_{tag}", "run_kernel_trace.csv")) as f:
+        rows = sorted(csv.DictReader(f), key=lambda r: int(r["Start_Timestamp"]))
+    starts = [i for i, r in enumerate(rows) if "begin_step_kernel" in r["Kernel_Name"]]
+    lo = starts[-(skip + nsteps)]
+    hi = starts[-skip] if skip else len(rows)
+    # not the next segment's state upload and its check
+    nxt = [i for i in range(lo, hi) if "set_scalars_kernel" in rows[i]["Kernel_Name"] or
+           "copyBuffer" in rows[i]["Kernel_Name"]]
+    win = rows[lo:nxt[0] if nxt else hi]
+    agg = collections.OrderedDict()
+    for r in win:
+        n = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        agg.setdefault(n, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    tot = sum(sum(v) for v in agg.values())
+    span = (int(win[-1]["End_Timestamp"]) - int(win[0]["Start_Timestamp"])) / 1e3
+    lines = ["rocprofv3 kernel statistics: " + desc + ".", "",
+             "command (REPO = the repository root on the GPU host):", "  cd /tmp && export TMPDIR=/tmp",
+             f"  rocprofv3 --kernel-trace --stats --output-format csv -d $REPO/gpurun_out/pk_{tag} -o run -- "
+             f"python3 $REPO/bench.py {bargs}",
+             f"  python3 $REPO/bench.py --summarize-trace {tag} --counters-dir $REPO/gpurun_out", "",
+             f"{'kernel':66s} {'calls':>5s} {'avg us':>8s} {'min us':>8s} {'max us':>8s} {'%':>6s}"]
+    for n, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{n[:66]:66s} {len(v):5d} {sum(v) / len(v):8.1f} {min(v):8.1f} {max(v):8.1f} "
+                     f"{100 * sum(v) / tot:6.2f}")
+    fl = [d for n, v in agg.items() if "fluid_" in n for d in v]
+    lines += ["", f"fluid sweep class: {len(fl)} launches, average {sum(fl) / max(1, len(fl)):.1f} us",
+              f"sum of kernel time per double step: {tot / nsteps:.1f} us; first dispatch to last, per double step: "
+              f"{span / nsteps:.1f} us", "",
+              "Template arguments: fluid_lanes_kernel<T, GRAV, HSE, LIM, CFL, NU> (x sweep, DPP lane streaming; CFL = "
+              "the last L_x of a step with the fused CFL reduction); fluid_strided_kernel<T, D, GRAV, HSE, LIM, NU> "
+              "(y, z sweeps, and the x sweep on the strided policy); field_lanes_kernel<T, LIM, NU> (B_x); "
+              "field_strided_kernel<T, D, LIM, NU> (B_y, B_z)."]
+    with open(os.path.join(ROOT, "profiles", f"kernels_{tag}.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines[7:]))
+
+
+def batch_cells(nboxes=2048):
+    import fish_inputs as fi
+
+    return sum(s["edge"] ** 3 for s in fi.batch_box_specs(nboxes))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -655,6 +896,9 @@ def main():
                     help="sphere workload: unsplit source (default) or split kicks, Sect. 2.3")
     ap.add_argument("--stretch", type=float, default=0.0,
                     help="box workload on an irregular mesh: widths 1 + STRETCH sin(2 pi x + axis) (Sect. 2.5)")
+    ap.add_argument("--x-strided", type=int, default=0, metavar="SEG",
+                    help="box workload: run the x fluid sweep with the strided policy (lanes along y, segments "
+                         "of SEG cells) instead of the lanes policy, to measure that alternative")
     ap.add_argument("--boxes", type=int, default=2048)
     ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
     ap.add_argument("--single-sample", type=int, default=8, help="boxes per size for the single-box comparison")
@@ -664,7 +908,17 @@ def main():
     ap.add_argument("--serve-sat", type=int, default=48)
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[0.25, 0.5, 0.75, 1.0, 1.25])
     ap.add_argument("--chunk", type=int, default=5)
+    ap.add_argument("--summarize", choices=tuple(PROFILED), default=None,
+                    help="no run: write the committed counter summary of a workload from its rocprofv3 passes")
+    ap.add_argument("--summarize-trace", choices=tuple(TRACED), default=None,
+                    help="no run: write the committed kernel-trace summary of a traced run")
+    ap.add_argument("--counters-dir", default=os.path.join(ROOT, "gpurun_out"))
     args = ap.parse_args()
+    if args.summarize_trace:
+        return summarize_trace(args.summarize_trace, args.counters_dir)
+    if args.summarize:
+        cells = {"box": args.n ** 3, "sphere": 512 ** 3, "batch": batch_cells(args.boxes)}[args.summarize]
+        return summarize_counters(args.summarize, args.counters_dir, cells)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(boxes are independent; a multi-GPU slab decomposition is a design note, not a run)", file=sys.stderr)
@@ -708,7 +962,8 @@ def main():
     for prec in ("fp32",) + (() if args.no_fp64 else ("fp64",)):
         log(f"GPU {prec}: {args.warmup} warmup + {args.steps} timed steps")
         res[prec] = run_gpu(fish, torch, st, n, prec, args.steps, args.warmup, cfl, args.segment,
-                            autotune=not args.no_autotune, limiter=LIMITERS[args.limiter], stretch=args.stretch)
+                            autotune=not args.no_autotune, limiter=LIMITERS[args.limiter], stretch=args.stretch,
+                            x_strided=args.x_strided)
         r = res[prec]
         log(f"  {r['wall'] * 1e3 / args.steps:.3f} ms/step, fluid launch avg "
             f"{r['fluid_ms'] / max(1, r['fluid_launches']):.3f} ms, state_ok={r['state_ok']}")
@@ -720,7 +975,7 @@ def main():
     bytes_fluid = ncell * 13 * esize  # reads rho, m, E and the three face fields; writes rho, m, E
     achieved = bytes_fluid / fluid_avg_s / 1e9
     # the counters were taken on the default configuration's kernels only
-    default_kernels = args.limiter == "vanleer" and not args.stretch
+    default_kernels = args.limiter == "vanleer" and not args.stretch and not args.x_strided
     traffic, valu_insts = (load_counters("fluid_sweep_traffic_256.json", esize, ncell) if default_kernels
                            else (None, None))
     # the same launches against the VALU issue peak: the step is bound by
@@ -756,6 +1011,8 @@ def main():
                         "switch": "van Leer where subsonic, minmod where supersonic"}[args.limiter],
             "autotuned": r["tuned"],
             "mesh": "uniform" if not args.stretch else f"irregular: widths 1 + {args.stretch} sin(2 pi x + axis), Sect. 2.5",
+            "x_fluid_layout": "lanes policy (rows streamed through the wavefront)" if not args.x_strided else
+                              f"strided policy, lanes along y, segments of {args.x_strided} (CFL by the check kernel)",
         },
         "latency_ms": {"p50": pct(r["step_ms"], 50), "p99": pct(r["step_ms"], 99)},
         "step_roofline": {"bytes_per_cell": 384, "achieved_GBs": value * 384 / 1e9, "peak_GBs": HBM_PEAK_GBS,

@@ -207,7 +207,10 @@ enum {
  * rows instead of contiguous pencils, for the x field kind two stream
  * positions per lane instead of one, for the check kind the CFL speed of a
  * step's new state reduced by the check kernel after the last x sweep
- * instead of inside it (the same value either way).  targets_out (may be NULL) receives
+ * instead of inside it (the same value either way).  The x fluid kind has
+ * an alternative layout too, the strided policy with the lanes along y and
+ * the shape as its segment length; the autotuner does not try it (set it
+ * with fish_set_shape), and with it the check kernel reduces the CFL speed.  targets_out (may be NULL) receives
  * FISH_NUM_KINDS chosen values: the shape in bits 0-15, the block order
  * (1 = XCD-grouped) in bit 16, the alternative layout in bit 17.
  * Results do not depend on the shapes (each cell is computed by the same

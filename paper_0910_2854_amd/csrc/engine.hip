@@ -588,6 +588,11 @@ static long long strided_waves(long long nA, long long nO, int groups) {
 static long long kind_waves(const HostBox& b, int kind, int target, int groups, int* par) {
   switch (kind) {
     case K_FLUID_X: {
+      if (groups) {  // the strided policy along x: lanes along y, segments of the rows
+        const int seg = std::max(1, std::min(target, b.n[0]));
+        *par = seg;
+        return strided_waves(b.n[1], b.n[2], groups) * ceil_div(b.n[0], seg);
+      }
       const int rpw = std::max(1, target / (b.n[0] + 6));
       *par = rpw;
       return ceil_div((long long)b.n[1] * b.n[2], rpw);
@@ -627,7 +632,7 @@ static long long kind_waves(const HostBox& b, int kind, int target, int groups, 
 // fish_set_shape or the autotuner is used as set.
 static int single_box_target(const HostBox& b, int kind, int target, int groups) {
   int lo = 1;
-  if (kind == K_FLUID_X) lo = b.n[0] + 6;
+  if (kind == K_FLUID_X) lo = groups ? 8 : b.n[0] + 6;
   if (kind == K_FIELD_X) lo = b.n[0] + 8;
   if (kind == K_FLUID_Y || kind == K_FLUID_Z || kind == K_FIELD_Y || kind == K_FIELD_Z) lo = 8;
   int par = 1;
@@ -638,6 +643,7 @@ static int single_box_target(const HostBox& b, int kind, int target, int groups)
 // Segments per pencil of a y/z kind, ceil(n_d / segment length); 0 for the
 // other kinds.
 static int kind_segments(const HostBox& b, int kind, int par) {
+  if (kind == K_FLUID_X) return (b.n[0] + par - 1) / par;  // read by the strided layout only
   if (kind == K_FLUID_Y || kind == K_FIELD_Y) return (b.n[1] + par - 1) / par;
   if (kind == K_FLUID_Z || kind == K_FIELD_Z) return (b.n[2] + par - 1) / par;
   return 0;
@@ -887,15 +893,15 @@ int Engine::check_cfl_all() {
 }
 
 // The launches of one double step with every box's CFL step: dt from the
-// CFL speed of the current state, the twelve sub-operators of Eqs. (12)-(13)
-// in symmetric order, the CFL speed of the new state reduced by the last
-// sweep, t += 2 dt.
+// CFL speed of the current state (with t += 2 dt and the maximum cleared in
+// the same kernel), the twelve sub-operators of Eqs. (12)-(13) in symmetric
+// order, the CFL speed of the new state reduced by the last sweep.
 int Engine::enqueue_step_cfl() {
   const int nb = (int)table_slots.size();
   const BoxDesc* tb = (const BoxDesc*)table.ptr;
   Scalars* sc = (Scalars*)scal.ptr;
   int rc;
-  hipLaunchKernelGGL(finalize_dt_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream, tb, nb, sc);
+  hipLaunchKernelGGL(begin_step_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream, tb, nb, sc, 0.0);
   if ((rc = launch_check())) return rc;
   for (int d = 0; d < 3; ++d) {
     if ((rc = run_sub(0, d))) return rc;
@@ -906,25 +912,20 @@ int Engine::enqueue_step_cfl() {
     if ((rc = run_sub(0, d))) return rc;
   }
   if ((rc = run_sub(1, 0))) return rc;
-  if ((rc = last_sweep_and_cfl())) return rc;
-  hipLaunchKernelGGL(advance_time_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream, tb, nb, sc);
-  return launch_check();
+  return last_sweep_and_cfl();
 }
 
 // The last L_x of a step and the CFL speed of the state it leaves: reduced by
 // the sweep itself, or by the check kernel after it (tuning choice; the same
 // per-cell function, so the same value either way).
 int Engine::last_sweep_and_cfl() {
-  const int nb = (int)table_slots.size();
-  const BoxDesc* tb = (const BoxDesc*)table.ptr;
-  Scalars* sc = (Scalars*)scal.ptr;
   int rc;
-  if (tuning.groups[K_CHECK]) {
+  // the strided x layout has no fused reduction: the check kernel follows it
+  if (tuning.groups[K_CHECK] || tuning.groups[K_FLUID_X]) {
     if ((rc = run_sub(0, 0))) return rc;
     return esize == 8 ? launch_check_cfl<double>() : launch_check_cfl<float>();  // resets cmax first
   }
-  hipLaunchKernelGGL(reset_cmax_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream, tb, nb, sc);
-  last_fluid_cfl = true;
+  last_fluid_cfl = true;  // the step's begin_step_kernel cleared the maximum
   rc = run_sub(0, 0);
   last_fluid_cfl = false;
   return rc;
@@ -942,7 +943,7 @@ int Engine::strang_step(double dt) {
     if ((rc = enqueue_step_cfl())) return rc;
   } else {
     // a given step size (one box): every sub-operator of size dt
-    hipLaunchKernelGGL(set_dt_kernel, dim3(grid_for((long long)table_slots.size())), dim3(kBlock), 0, cfg.stream,
+    hipLaunchKernelGGL(begin_step_kernel, dim3(grid_for((long long)table_slots.size())), dim3(kBlock), 0, cfg.stream,
                        (const BoxDesc*)table.ptr, (int)table_slots.size(), (Scalars*)scal.ptr, dt);
     if ((rc = launch_check())) return rc;
     for (int d = 0; d < 3; ++d) {
@@ -955,10 +956,6 @@ int Engine::strang_step(double dt) {
     }
     if ((rc = run_sub(1, 0))) return rc;
     if ((rc = last_sweep_and_cfl())) return rc;
-    const int nb = (int)table_slots.size();
-    hipLaunchKernelGGL(advance_time_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, cfg.stream,
-                       (const BoxDesc*)table.ptr, nb, (Scalars*)scal.ptr);
-    if ((rc = launch_check())) return rc;
   }
   for (int s : table_slots) boxes[s].cfl_fresh = true;
   return 0;
@@ -971,8 +968,6 @@ int Engine::set_shape(int kind, int value) {
   if (kind < 0 || kind >= K_NUM) return fail(1, "no such kernel kind");
   const int target = value & 0xFFFF, remap = (value >> 16) & 1, alt = (value >> 17) & 1;
   if (target < 1 || (value >> 18) != 0) return fail(1, "bad shape value");
-  if (alt && kind == K_FLUID_X)
-    return fail(1, "this kind has no alternative layout");
   tuning.target[kind] = target;
   tuning.remap[kind] = remap;
   tuning.groups[kind] = alt;
@@ -1267,17 +1262,8 @@ void launch_check(const CheckLaunch<T>& L, hipStream_t stream) {
 template void launch_check<float>(const CheckLaunch<float>&, hipStream_t);
 template void launch_check<double>(const CheckLaunch<double>&, hipStream_t);
 
-void launch_reset_cmax(const BoxDesc* boxes, int nb, Scalars* sc, hipStream_t stream) {
-  hipLaunchKernelGGL(reset_cmax_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, stream, boxes, nb, sc);
-}
-void launch_finalize_dt(const BoxDesc* boxes, int nb, Scalars* sc, hipStream_t stream) {
-  hipLaunchKernelGGL(finalize_dt_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, stream, boxes, nb, sc);
-}
-void launch_set_dt(const BoxDesc* boxes, int nb, Scalars* sc, double dt, hipStream_t stream) {
-  hipLaunchKernelGGL(set_dt_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, stream, boxes, nb, sc, dt);
-}
-void launch_advance_time(const BoxDesc* boxes, int nb, Scalars* sc, hipStream_t stream) {
-  hipLaunchKernelGGL(advance_time_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, stream, boxes, nb, sc);
+void launch_begin_step(const BoxDesc* boxes, int nb, Scalars* sc, double dt, hipStream_t stream) {
+  hipLaunchKernelGGL(begin_step_kernel, dim3(grid_for(nb)), dim3(kBlock), 0, stream, boxes, nb, sc, dt);
 }
 
 int selftest_lane_shift(int device, float* out128) {

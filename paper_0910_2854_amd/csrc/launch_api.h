@@ -18,6 +18,7 @@ struct SweepSel {
   int hse = 0;
   bool nonuniform = false; // per-cell widths (the launch carries them)
   bool lanes2 = false;     // x field sweep: two stream positions per lane (uniform meshes)
+  bool x_strided = false;  // x fluid sweep without the CFL reduction: the strided policy, lanes along y
   hipStream_t stream = nullptr;
 };
 
@@ -34,13 +35,11 @@ void launch_field_sweep(const SweepSel& s, const FieldLaunch<T>& L);
 template <typename T>
 void launch_check(const CheckLaunch<T>& L, hipStream_t stream);
 
-// Per-box step scalars over the first nb boxes of a table (engine.hip):
-// reset the CFL maximum; dt = k / C (Eq. 14) with the step factors; a given
-// dt with its factors; t += 2 dt.
-void launch_reset_cmax(const BoxDesc* boxes, int nb, Scalars* sc, hipStream_t stream);
-void launch_finalize_dt(const BoxDesc* boxes, int nb, Scalars* sc, hipStream_t stream);
-void launch_set_dt(const BoxDesc* boxes, int nb, Scalars* sc, double dt, hipStream_t stream);
-void launch_advance_time(const BoxDesc* boxes, int nb, Scalars* sc, hipStream_t stream);
+// The start of a double step over the first nb boxes of a table
+// (engine.hip): the step size (dt > 0 as given, else the CFL step of Eq. 14
+// from the boxes' CFL maxima) with its factors, t += 2 dt, and the CFL
+// maximum cleared for the step's last sweep.
+void launch_begin_step(const BoxDesc* boxes, int nb, Scalars* sc, double dt, hipStream_t stream);
 
 // The work shape of a box alone in its table at the default tuning (as the
 // engine plans it): per kind the parameter of BoxDesc::par, the segments per

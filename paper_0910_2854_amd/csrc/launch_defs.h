@@ -12,11 +12,13 @@ namespace fish {
 
 // ------------------------------------------------------------ fluid sweeps
 template <typename T, int D, int GRAV, bool HSE, int LIM, bool NU>
-void fluid_kernel(const FluidLaunch<T>& L, bool cfl, hipStream_t stream) {
+void fluid_kernel(const FluidLaunch<T>& L, bool cfl, bool x_strided, hipStream_t stream) {
   if (L.wl.nwaves == 0) return;
   const dim3 grid(grid_for((long long)L.wl.nwaves * 64));
   if constexpr (D == 0) {
-    if (cfl)
+    if (x_strided && !cfl)
+      hipLaunchKernelGGL((fluid_strided_kernel<T, 0, GRAV, HSE, LIM, NU>), grid, dim3(kBlock), 0, stream, L);
+    else if (cfl)
       hipLaunchKernelGGL((fluid_lanes_kernel<T, GRAV, HSE, LIM, true, NU>), grid, dim3(kBlock), 0, stream, L);
     else
       hipLaunchKernelGGL((fluid_lanes_kernel<T, GRAV, HSE, LIM, false, NU>), grid, dim3(kBlock), 0, stream, L);
@@ -28,9 +30,9 @@ void fluid_kernel(const FluidLaunch<T>& L, bool cfl, hipStream_t stream) {
 template <typename T, int D, int GRAV, bool HSE, int LIM>
 void fluid_mesh(const SweepSel& s, const FluidLaunch<T>& L, bool cfl) {
   if (s.nonuniform)
-    fluid_kernel<T, D, GRAV, HSE, LIM, true>(L, cfl, s.stream);
+    fluid_kernel<T, D, GRAV, HSE, LIM, true>(L, cfl, s.x_strided, s.stream);
   else
-    fluid_kernel<T, D, GRAV, HSE, LIM, false>(L, cfl, s.stream);
+    fluid_kernel<T, D, GRAV, HSE, LIM, false>(L, cfl, s.x_strided, s.stream);
 }
 
 template <typename T, int D, int LIM>
@@ -85,6 +87,7 @@ inline SweepSel Engine::sweep_sel() const {
   s.hse = cfg.hse;
   s.nonuniform = nonuniform;
   s.lanes2 = tuning.groups[K_FIELD_X] != 0;
+  s.x_strided = tuning.groups[K_FLUID_X] != 0;
   s.stream = cfg.stream;
   return s;
 }

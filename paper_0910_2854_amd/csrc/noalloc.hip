@@ -167,18 +167,17 @@ struct Step {
   } while (0)
 
 // The launches of one double step: the step size (given, or the CFL step of
-// the state: its CFL speed reduced by the check kernel, then dt = k / C),
-// the twelve sub-operators in symmetric order with the CFL speed of the new
-// state reduced by the last one, and the report.
+// the state: its CFL speed reduced by the check kernel, then dt = k / C, with
+// the maximum cleared for the last sweep), the twelve sub-operators in
+// symmetric order with the CFL speed of the new state reduced by the last
+// one, and the report.
 template <typename T>
 int enqueue(Step<T>& s, double dt, fish_step_report* report, std::string* msg) {
   if (dt == 0.0) {
     s.check();
     LAUNCHED();
-    launch_finalize_dt(s.table, 1, s.sc, s.sel.stream);
-  } else {
-    launch_set_dt(s.table, 1, s.sc, dt, s.sel.stream);
   }
+  launch_begin_step(s.table, 1, s.sc, dt, s.sel.stream);
   LAUNCHED();
   s.template fluid<0>(false);
   LAUNCHED();
@@ -201,8 +200,6 @@ int enqueue(Step<T>& s, double dt, fish_step_report* report, std::string* msg) {
   s.template fluid<1>(false);
   LAUNCHED();
   s.template field<0>();
-  LAUNCHED();
-  launch_reset_cmax(s.table, 1, s.sc, s.sel.stream);
   LAUNCHED();
   s.template fluid<0>(true);
   LAUNCHED();

@@ -46,15 +46,37 @@ __global__ void finalize_dt_kernel(const BoxDesc* boxes, int nb, Scalars* sc) {
   set_step(s, boxes[i].g, dt);
 }
 
-__global__ void advance_time_kernel(const BoxDesc* boxes, int nb, Scalars* sc) {
+// The start of a double step, one thread per box: the step size of every
+// sub-operator (dt > 0 as given, else k / C from the CFL speed of the current
+// state, Eq. 14, clamped to an end time, as finalize_dt_kernel), the time the
+// step reaches (t + 2 dt, Eqs. 12-13) and the count of steps taken with
+// dt > 0, and the CFL maximum cleared for the reduction fused into the step's
+// last sweep (no other sweep of the step touches it).
+__global__ void begin_step_kernel(const BoxDesc* boxes, int nb, Scalars* sc, double dt_given) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nb) {
-    Scalars* s = sc + boxes[i].slot;
-    if (s->dt > 0.0) {
-      s->t += 2.0 * s->dt;
-      s->taken += 1;
+  if (i >= nb) return;
+  Scalars* s = sc + boxes[i].slot;
+  if (dt_given > 0.0) {
+    set_step(s, boxes[i].g, dt_given);
+  } else {
+    const double cmax = __longlong_as_double((long long)s->cmax_bits);
+    double dt = 0.0;
+    if (!(cmax > 0.0) || !isfinite(cmax) || s->status) {
+      s->status |= 1;
+    } else {
+      dt = boxes[i].cfl / cmax;
+      if (s->has_end) {
+        const double rest = s->t_end - s->t;
+        dt = rest > 0.0 ? fmin(dt, 0.5 * rest) : 0.0;
+      }
     }
+    set_step(s, boxes[i].g, dt);
   }
+  if (s->dt > 0.0) {
+    s->t += 2.0 * s->dt;
+    s->taken += 1;
+  }
+  s->cmax_bits = 0ull;
 }
 
 // A given step size for every box of the table.

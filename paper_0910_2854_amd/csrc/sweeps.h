@@ -543,12 +543,14 @@ __device__ __forceinline__ bool strided_map(int wave, int nA, int nO, int nseg, 
   return true;
 }
 
-// Strided policy (D = y or z): one lane per pencil segment, lanes along x.
+// Strided policy: one lane per pencil segment.  For D = y or z the lanes
+// walk along x (each load of a wave is 64 consecutive values); for D = x (an
+// alternative to the lanes policy) they walk along y, so that a wave's load
+// touches 64 rows, one value of each.
 template <typename T, int D, int GRAV, bool HSE, int LIM, bool NU>
 __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidLaunch<T> L) {
-  static_assert(D != 0, "x sweeps use the lanes policy");
-  constexpr int A = 0;  // lanes walk along x
-  constexpr int O = 3 - D;
+  constexpr int A = D == 0 ? 1 : 0;
+  constexpr int O = D == 0 ? 2 : 3 - D;
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   const BoxDesc* d;
   int lw;
@@ -650,51 +652,54 @@ __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidLaunch<T> L) {
 }
 
 // Speeds of one cell for Eq. (14)-(15): sp[d] = |v_d| + c_F,d on the active
-// axes (0 on an axis with one cell), with the pressure recovered in FP64;
-// also flags a bad state (rho <= 0, p <= 0 or a non-finite value).  The
-// division by h_d is left to cfl_of: it is monotonic, so the maximum of the
-// divided speeds is the divided maximum, bitwise.
+// axes (0 on an axis with one cell), in the storage precision, with the
+// pressure recovered in FP64; also flags a bad state (rho <= 0, p <= 0 or a
+// non-finite value).  The pressure takes every conserved value and the cell's
+// field, so a non-finite one leaves rho or p non-finite or p <= 0, and a
+// speed that is not finite leaves their sum non-finite: four tests instead of
+// one per value.  The division by h_d is left to cfl_of: it is monotonic, so
+// the maximum of the divided speeds is the divided maximum, bitwise.
 template <typename T>
-__device__ __forceinline__ void cell_cfl_speeds(const T* u, const T* b, double gamma, const Geo& g, double* sp,
-                                                int& bad) {
+__device__ __forceinline__ void cell_cfl_speeds(const T* u, const T* b, double gamma, const Geo& g, T* sp, int& bad) {
   T b2;
   const T p = pressure<T>(u, b, gamma - 1.0, &b2);
   const T ri = rcp(u[RHO]);
   const T a2 = (T)gamma * p * ri;
   const T q = a2 + b2 * ri;
-  bool ok = u[RHO] > T(0) && p > T(0);
-#pragma unroll
-  for (int i = 0; i < 5; ++i) ok = ok && isfinite(u[i]);
+  T sum = T(0);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    sp[d] = 0.0;
+    sp[d] = T(0);
     if (g.n[d] > 1) {
       const T disc = q * q - T(4) * a2 * b[d] * b[d] * ri;
       const T cf = fsqrt(T(0.5) * (q + fsqrt(disc < T(0) ? T(0) : disc)));
-      sp[d] = (double)fabs(u[MX + d] * ri) + (double)cf;
-      ok = ok && isfinite(sp[d]);
+      sp[d] = fabs(u[MX + d] * ri) + cf;
+      sum += sp[d];
     }
   }
+  const bool ok = u[RHO] > T(0) && p > T(0) && isfinite(u[RHO]) && isfinite(p) && isfinite(sum);
   if (!ok) bad = 1;
 }
 
 // max over the active axes of smax[d] / h_d (Eq. 15).
-__device__ __forceinline__ double cfl_of(const double* smax, const Geo& g) {
+template <typename T>
+__device__ __forceinline__ double cfl_of(const T* smax, const Geo& g) {
   double c = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d)
-    if (g.n[d] > 1) c = fmax(c, smax[d] / g.h[d]);
+    if (g.n[d] > 1) c = fmax(c, (double)smax[d] / g.h[d]);
   return c;
 }
 
 // Eq. (70), the CFL condition on an irregular mesh: max over the active axes
 // of one cell's speed over its own width along that axis.
-__device__ __forceinline__ double cfl_of_cell(const double* sp, double wx, double wy, double wz, const Geo& g) {
+template <typename T>
+__device__ __forceinline__ double cfl_of_cell(const T* sp, double wx, double wy, double wz, const Geo& g) {
   const double w[3] = {wx, wy, wz};
   double c = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d)
-    if (g.n[d] > 1) c = fmax(c, sp[d] / w[d]);
+    if (g.n[d] > 1) c = fmax(c, (double)sp[d] / w[d]);
   return c;
 }
 
@@ -742,7 +747,7 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
   const int nit = (npos + STEP - 1) / STEP;
   const FluidConsts<T> k = fluid_consts(a, D);
   FluidHist<T, HSE> hA, hB;  // unused by the carry-free policy
-  double smax[3] = {0.0, 0.0, 0.0};
+  T smax[3] = {T(0), T(0), T(0)};  // per axis, the largest |v_d| + c_F,d of the lane's cells
   double cnu = 0.0;  // irregular mesh: the CFL speed over widths, per cell
   int bad = 0;
   const unsigned st1 = (unsigned)g.st[1], st2 = (unsigned)g.st[2];  // arrays < 2^32 bytes
@@ -760,7 +765,6 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
     T u[5], u3[5];
     Vec<T, 3> bc;
     T phi, gh;
-    T b3[3];      // cell-centred field of the output cell (CFL only)
     T w[5], wy, wz;  // irregular mesh: widths of cells c-4 .. c along x; the row's y, z widths
     unsigned o3;  // byte offset of the output cell c-3
     int co;       // output cell index along x
@@ -816,13 +820,6 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
     in.o3 = (base + (unsigned)map_cell_near(cpos - 3, nx, g.bc[0])) * z4;
 #pragma unroll
     for (int i = 0; i < 5; ++i) in.u3[i] = ld(a.u[i], in.o3);
-    if (CFL) {
-      const unsigned g0 = (base + (unsigned)map_face_near(cpos - 3, nx, g.bc[0])) * z4;
-      const unsigned g1 = (base + (unsigned)map_face_near(cpos - 2, nx, g.bc[0])) * z4;
-      in.b3[0] = T(0.5) * (ld(a.b[0], g0) + ld(a.b[0], g1));
-      in.b3[1] = T(0.5) * (ld(a.b[1], in.o3) + ld(a.b[1], in.o3 + dy));
-      in.b3[2] = T(0.5) * (ld(a.b[2], in.o3) + ld(a.b[2], in.o3 + dz));
-    }
     rc.advance(L, rows, ny, st1, up, STEP);
     return in;
   };
@@ -836,9 +833,14 @@ __global__ __launch_bounds__(256) void fluid_lanes_kernel(FluidLaunch<T> FL) {
       for (int i = 0; i < 5; ++i) st(a.uo[i], in.o3, un[i]);
     }
     if (CFL) {
+      // the cell-centred field of the output cell c-3 is the one position
+      // c-3 loaded, three lanes down (the same row for every output lane)
+      T b3[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) b3[j] = lane_shr(lane_shr(lane_shr(in.bc.v[j])));
       int cell_bad = 0;
-      double sp[3];
-      cell_cfl_speeds<T>(un, in.b3, a.gamma, g, sp, cell_bad);
+      T sp[3];
+      cell_cfl_speeds<T>(un, b3, a.gamma, g, sp, cell_bad);
       if (out) {
         if (NU) {
           cnu = fmax(cnu, cfl_of_cell(sp, (double)in.w[1], (double)in.wy, (double)in.wz, g));
@@ -1289,6 +1291,108 @@ __global__ __launch_bounds__(256) void field_strided_kernel(FieldLaunch<T> FL) {
   }
 }
 
+// The x field sweep with one face row (y, z) per wave, on a uniform mesh.
+// The row, its base and its neighbour offsets are wave-uniform, so every
+// load and store takes a scalar base and the lane's x offset only, and an
+// iteration that lies inside the row (every cell it reaches in [0, n_x))
+// takes the x index unmapped.  Iteration it covers positions
+// it STEP .. it STEP + STEP - 1 of the row (the last one partly), its first
+// HALO lanes recomputing the positions before them as in the general path.
+template <typename T, int LIM>
+__device__ __forceinline__ void field_lanes_row(const FieldArgs<T>& a, const FieldConsts<T>& k, int y, int zc) {
+  const Geo& g = a.g;
+  const int nx = g.n[0];
+  const bool outx = g.bc[0] == 1;
+  const int L = nx + 8;
+  constexpr int HALO = 8, STEP = 64 - HALO;
+  const int lane = threadIdx.x & 63;
+  constexpr unsigned z = sizeof(T);
+  const unsigned st1 = (unsigned)g.st[1], st2 = (unsigned)g.st[2];
+  RowOffsets ro;
+  row_offsets<T>(g, y, zc, (unsigned)y * st1 + (unsigned)zc * st2, ro);
+  const bool own1 = zc < g.n[2], own2 = y < g.n[1];
+  auto at = [](const T* p, unsigned b) {
+    return in_sgpr((const T*)((const char*)p + (unsigned)__builtin_amdgcn_readfirstlane((int)b)));
+  };
+  auto at_out = [](T* p, unsigned b) {
+    return in_sgpr((T*)((char*)p + (unsigned)__builtin_amdgcn_readfirstlane((int)b)));
+  };
+  const unsigned cn[5] = {ro.ownc, ro.ownc + ro.c1m, ro.ownc + ro.c1p, ro.ownc + ro.c2m, ro.ownc + ro.c2p};
+  const T* md[5];
+  const T* rh[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    md[i] = at(a.md, cn[i]);
+    rh[i] = at(a.rho, cn[i]);
+  }
+  const T* bA = at(a.bt[0], ro.base);
+  const T* bB = at(a.bt[0], ro.base + ro.f1p);
+  const T* bC = at(a.bt[1], ro.base);
+  const T* bD = at(a.bt[1], ro.base + ro.f2p);
+  const T* bd = at(a.bd, ro.base);
+  T* o1 = at_out(a.bto[0], ro.base);
+  T* o2 = at_out(a.bto[1], ro.base);
+  T* od = at_out(a.bdo, ro.base);
+  RowHist<T> hA[4], hB[4];  // unused by the carry-free policy
+  struct In {
+    FieldIn<T> f;
+    unsigned oc, o4, of;  // x byte offsets of cells c and c-4 and of d-face c-3
+    int cpos;
+    bool valid;
+  };
+  auto load = [&](int it) {
+    In in;
+    const int p0 = it * STEP - HALO;  // position of lane 0 (uniform)
+    const int p = p0 + lane;
+    in.valid = lane >= HALO && p < L;
+    const int c0 = p0 - 4;            // cell index of lane 0
+    if (c0 >= 4 && c0 + 63 < nx) {    // uniform: the whole iteration inside the row
+      in.cpos = p - 4;
+      in.oc = (unsigned)in.cpos * z;
+      in.o4 = in.oc - 4 * z;
+      in.of = in.oc - 3 * z;
+    } else {
+      // clamped as in the general path: every index stays in the box
+      in.cpos = min(max(p, 0), L - 1) - 4;
+      in.oc = (unsigned)map_cell_near(in.cpos, nx, g.bc[0]) * z;
+      in.o4 = (unsigned)map_cell_near(in.cpos - 4, nx, g.bc[0]) * z;
+      in.of = (unsigned)map_face_near(in.cpos - 3, nx, g.bc[0]) * z;
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      in.f.md[i] = ld(md[i], in.oc);
+      in.f.rho[i] = ld(rh[i], in.oc);
+    }
+    in.f.b[0] = ld(bA, in.oc);
+    in.f.b[1] = ld(bB, in.oc);
+    in.f.b[2] = ld(bC, in.oc);
+    in.f.b[3] = ld(bD, in.oc);
+    in.f.b4a = ld(bA, in.o4);
+    in.f.b4c = ld(bC, in.o4);
+    in.f.bd3 = ld(bd, in.of);
+    return in;
+  };
+  auto compute = [&](const In& in, const RowHist<T>* hi, RowHist<T>* ho) {
+    T bn1, bn2, dbd;
+    field_compute<T, LIM, LaneShift, true, false>(in.f, k, FieldRowNU<T>{}, FieldPosNU<T>{}, hi, ho, bn1, bn2, dbd);
+    const int cb = in.cpos - 4;
+    if (in.valid && cb >= 0 && cb < nx) {
+      if (own1) st(o1, in.o4, bn1);
+      if (own2) st(o2, in.o4, bn2);
+    }
+    const int fd = in.cpos - 3;
+    if (in.valid && own1 && own2 && fd >= 0 && (fd < nx || (outx && fd == nx))) st(od, in.of, in.f.bd3 + dbd);
+  };
+  const int nit = (L + STEP - 1) / STEP;
+  In cur = load(0);
+  for (int it = 0; it < nit; it += 2) {
+    const In nxt = load(it + 1);
+    compute(cur, hA, hB);
+    cur = load(it + 2);
+    compute(nxt, hB, hA);
+  }
+}
+
 // Lanes policy (d = x): waves stream whole rows (y, z) of faces, each padded
 // by 4 positions before and 4 after.
 template <typename T, int LIM, bool NU>
@@ -1309,6 +1413,12 @@ __global__ __launch_bounds__(256) void field_lanes_kernel(FieldLaunch<T> FL) {
   const int lane = threadIdx.x & 63;
   const long long r0 = wave * a.rows_per_wave;
   if (r0 >= nrows) return;  // whole wave exits together
+  if (!NU && a.rows_per_wave == 1) {
+    const int r = __builtin_amdgcn_readfirstlane((int)r0);
+    const int zr = r / ry;
+    field_lanes_row<T, LIM>(a, field_consts<T, D>(a), r - zr * ry, zr);
+    return;
+  }
   const int rows = (int)min((long long)a.rows_per_wave, nrows - r0);
   const int npos = rows * L;
   // lanes 0..HALO-1 recompute the last positions of the previous iteration:
@@ -1615,7 +1725,7 @@ __global__ __launch_bounds__(256) void check_cfl_kernel(CheckLaunch<T> L) {
   const long long r = c / n0;
   int y = (int)(r % n1);
   int zz = (int)(r / n1);
-  double smax[3] = {0.0, 0.0, 0.0};
+  T smax[3] = {T(0), T(0), T(0)};
   double cnu = 0.0;                      // irregular mesh: per-cell speeds over widths
   const bool nu = L.wid[0] != nullptr;   // uniform across the launch
   const T* wx = nu ? L.wid[0] + d->woff[0] : nullptr;
@@ -1634,8 +1744,7 @@ __global__ __launch_bounds__(256) void check_cfl_kernel(CheckLaunch<T> L) {
     bc[0] = T(0.5) * (ld(b[0], o) + ld(b[0], (s + sx) * z4));
     bc[1] = T(0.5) * (ld(b[1], o) + ld(b[1], (s + sy) * z4));
     bc[2] = T(0.5) * (ld(b[2], o) + ld(b[2], (s + sz) * z4));
-    if (!isfinite(bc[0]) || !isfinite(bc[1]) || !isfinite(bc[2])) bad = 1;
-    double sp[3];
+    T sp[3];
     cell_cfl_speeds<T>(uc, bc, L.gamma, g, sp, bad);
     if (nu) {
       cnu = fmax(cnu, cfl_of_cell(sp, (double)wx[x], (double)wy[y], (double)wz[zz], g));

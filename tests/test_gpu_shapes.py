@@ -23,13 +23,14 @@ BOXES = [((40, 24, 20), (PERIODIC,) * 3, 1), ((33, 17, 9), (OUTFLOW,) * 3, 2), (
 VARIANTS = [(256, 8, 1, 1), (3072, 256, 0, 1), (768, 24, 1, 0), (384, 64, 0, 1)]
 
 
-def _run(n, bc, st, prec, variant):
+def _run(n, bc, st, prec, variant, **kw):
     import paper_0910_2854_amd as fish
-    g = fish.Box(*n, precision=prec, bc=bc)
+    g = fish.Box(*n, precision=prec, bc=bc, **kw)
     g.set_state(st)
     if variant is not None:
         xt, seg, remap, alt = variant
-        g.set_shape("fluid_x", xt, remap, 0)
+        # alt: the strided x fluid layout with the y/z segment length
+        g.set_shape("fluid_x", seg if alt else xt, remap, alt)
         g.set_shape("field_x", xt, remap, alt)
         for kind in ("fluid_y", "fluid_z", "field_y", "field_z"):
             g.set_shape(kind, seg, remap, alt)
@@ -64,5 +65,22 @@ def test_set_shape_rejects_bad_values():
     with pytest.raises(fish.FishError):
         g.set_shape("fluid_x", 0)
     with pytest.raises(fish.FishError):
-        g.set_shape("fluid_x", 768, 0, 1)  # no alternative layout for the x fluid sweep
+        g.set_shape("fluid_x", 768, 0, 2)  # outside the encoding
     g.close()
+
+
+@pytest.mark.parametrize("gravity", ["unsplit", "split"])
+def test_strided_x_layout_with_gravity_and_hse_gives_the_default_result_bitwise(gravity):
+    """The strided x fluid layout under both gravity forms with the
+    hydrostatic correction, outflow boundaries, FP64 and FP32."""
+    n, bc = (37, 22, 18), (OUTFLOW,) * 3
+    st = fi.sphere_state(n, 5)
+    for prec in ("fp64", "fp32"):
+        print(f"strided x {gravity} {prec}", flush=True)
+        ref = _run(n, bc, st, prec, None, gravity=gravity, hse=True)
+        for v in VARIANTS:
+            if not v[3]:
+                continue
+            got = _run(n, bc, st, prec, v, gravity=gravity, hse=True)
+            for k in FIELDS:
+                assert np.array_equal(got[k], ref[k]), (prec, v, k)
