@@ -501,7 +501,8 @@ def bench_serve(args, torch, fish, fi):
 
 def bench_sphere(args, torch, fish, fi):
     """512^3 stratified sphere: outflow on every face, unsplit gravity and HSE
-    subtraction, FP32 with FP64 pressure recovery, 50 double steps."""
+    subtraction, FP32 with FP64 pressure recovery, autotuned work shapes,
+    --steps double steps (20 by default)."""
     n = (args.n if args.n != 256 else 512,) * 3
     ncell = n[0] * n[1] * n[2]
     log(f"sphere {n}: generating")
@@ -512,6 +513,8 @@ def bench_sphere(args, torch, fish, fi):
     box.set_state(st)
     if args.no_cpu:
         del st
+    tuned = box.autotune(reps=3) if not args.no_autotune else None
+    log(f"  autotuned: {tuned}")
     for _ in range(args.warmup):
         box.strang_step(0.0)
     torch.cuda.synchronize()
@@ -552,7 +555,8 @@ def bench_sphere(args, torch, fish, fi):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{n[0]}^3 stratified sphere rho = 1/(1+(r/0.1)^2) with 1% noise, matching potential "
                                f"and hydrostatic pressure, beta 100, outflow boundaries, {args.gravity} gravity + HSE, "
-                               "gamma 5/3, CFL 0.5, FP32 with FP64 pressure recovery", "cells": ncell},
+                               "gamma 5/3, CFL 0.5, FP32 with FP64 pressure recovery", "cells": ncell,
+                   "autotuned": tuned},
         "latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99)},
         "step_roofline": {"bytes_per_cell": 408, "achieved_GBs": value * 408 / 1e9, "peak_GBs": HBM_PEAK_GBS,
                           "frac": value * 408 / 1e9 / HBM_PEAK_GBS},
@@ -674,7 +678,7 @@ PROFILED = {
     "box": ("256", "--no-cpu --no-fp64 --steps 2 --warmup 0 --segment 2",
             "256^3 FP32 random-Fourier box (Mach 1, beta 1, |k|<=16), van Leer, autotuned shapes", 13 * 4),
     "sphere": ("512_sphere", "--workload sphere --no-cpu --steps 2 --warmup 0",
-               "512^3 FP32 stratified sphere, outflow, unsplit gravity + HSE, default shapes", 14 * 4),
+               "512^3 FP32 stratified sphere, outflow, unsplit gravity + HSE, autotuned shapes", 14 * 4),
     "batch": ("batch", "--workload batch --no-cpu --steps 2 --warmup 0 --single-sample 0",
               "batch of 2048 FP32 boxes (edges 16-64), autotuned shapes, the eager double steps", 13 * 4),
 }
@@ -693,11 +697,11 @@ TRACED = {
                       "XCD-grouped blocks) instead of the lanes policy, the CFL speed then from the check kernel; the "
                       "5 headline double steps", 5, 5),
     "512_sphere": ("--workload sphere --no-cpu --steps 5 --warmup 1",
-                   "512^3 stratified sphere, outflow, unsplit gravity + HSE, FP32 with FP64 pressure recovery, default "
-                   "shapes; the 5 headline double steps (2 hooked steps follow)", 5, 2),
+                   "512^3 stratified sphere, outflow, unsplit gravity + HSE, FP32 with FP64 pressure recovery, "
+                   "autotuned shapes; the 5 headline double steps (2 hooked steps follow)", 5, 2),
     "batch": ("--workload batch --no-cpu --steps 5 --warmup 1 --single-sample 0",
               "batch of 2048 periodic FP32 boxes (edges 16-64), autotuned shapes; the 5 timed double steps, replays "
-              "of the captured graph (5 eager steps follow)", 5, 5),
+              "of the captured graph (5 eager and 2 hooked steps follow)", 5, 7),
 }
 
 
@@ -765,9 +769,11 @@ def summarize_counters(workload, outdir, cells, nsteps=2):
                         c[r["Counter_Name"]] += float(r["Counter_Value"])
         calib = {"probe": f"bench.py {COPY_PROBE}: three 1 GiB device-to-device copies",
                  "read_GiB_per_copy": _fetch_bytes(c) / 3 / 2 ** 30, "write_GiB_per_copy": _write_bytes(c) / 3 / 2 ** 30}
+    ran = [(sub, c) for sub, c in PMC_PASSES
+           if os.path.exists(os.path.join(outdir, f"pmc_{tag}_{sub}", "run_counter_collection.csv"))]
     cmds = ["cd /tmp && export TMPDIR=/tmp"] + [
         f"rocprofv3 --pmc {c} --output-format csv -d $REPO/gpurun_out/pmc_{tag}_{sub} -o run -- "
-        f"python3 $REPO/bench.py {bargs}" for sub, c in PMC_PASSES] + [
+        f"python3 $REPO/bench.py {bargs}" for sub, c in ran] + [
         f"rocprofv3 --pmc {PMC_PASSES[i][1]} --output-format csv -d $REPO/gpurun_out/pmccopy_{PMC_PASSES[i][0]} -o run "
         f"-- python3 $REPO/bench.py {COPY_PROBE}" for i in (0, 1)] + [
         f"python3 $REPO/bench.py --summarize {workload} --counters-dir $REPO/gpurun_out"]
@@ -811,10 +817,11 @@ def summarize_counters(workload, outdir, cells, nsteps=2):
         f, w = _fetch_bytes(a) / k, _write_bytes(a) / k
         al = {"fluid": fluid_bpc, "field": 8 * 4, "check": 8 * 4}[kind] * cells
         valu = a.get("SQ_INSTS_VALU", 0)
+        int32 = (f"{a['SQ_INSTS_VALU_INT32'] * 64 / k / cells:10.1f}" if "SQ_INSTS_VALU_INT32" in a
+                 else f"{'n/a':>10s}")
         lines.append(f"{n.replace('fish::', '')[:58]:58s} {k:3d} {d:7.1f} {f / 1e6:9.1f} {w / 1e6:9.1f} {al / 1e6:8.1f} "
                      f"{(f + w) / al:6.2f} {((f + w) / d / 1e6) if d else 0:5.2f} {valu * 64 / k / cells:9.1f} "
-                     f"{a.get('SQ_INSTS_VALU_INT32', 0) * 64 / k / cells:10.1f} "
-                     f"{(valu / k * 4 / 1024 / (d * 1e-6 * 2.4e9)) if d else 0:9.2f}")
+                     f"{int32} {(valu / k * 4 / 1024 / (d * 1e-6 * 2.4e9)) if d else 0:9.2f}")
     with open(os.path.join(ROOT, "profiles", f"counters_{tag}.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines[-12:]))
