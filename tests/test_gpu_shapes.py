@@ -17,7 +17,9 @@ pytestmark = pytest.mark.gpu
 FIELDS = ("cell", "bx", "by", "bz")
 
 BOXES = [((40, 24, 20), (PERIODIC,) * 3, 1), ((33, 17, 9), (OUTFLOW,) * 3, 2), ((150, 6, 5), (PERIODIC,) * 3, 3),
-         ((70, 66, 9), (PERIODIC, OUTFLOW, PERIODIC), 4)]
+         ((70, 66, 9), (PERIODIC, OUTFLOW, PERIODIC), 4),
+         # rows long enough for the x field sweep's patches (sides 2 and 4, partial at the box edges)
+         ((160, 14, 11), (PERIODIC, OUTFLOW, OUTFLOW), 5), ((200, 9, 7), (OUTFLOW, PERIODIC, PERIODIC), 6)]
 
 # (x kinds: positions per wave, y/z kinds: segment length, xcd block order, alternative layout)
 VARIANTS = [(256, 8, 1, 1), (3072, 256, 0, 1), (768, 24, 1, 0), (384, 64, 0, 1)]
