@@ -257,7 +257,11 @@ int step_noalloc(const fish_params* p, void* const state[8], void* const work[8]
   if (check_runtime(p->stream, true, msg)) return FISH_ERR_DEVICE;
 
   int count = 0, prev = -1;
-  if (hipGetDeviceCount(&count) != hipSuccess || p->device < 0 || p->device >= count || p->device >= kMaxDevices) {
+  if (hipGetDeviceCount(&count) != hipSuccess) {
+    *msg = "hipGetDeviceCount failed (no HIP device?)";
+    return FISH_ERR_DEVICE;
+  }
+  if (p->device < 0 || p->device >= count || p->device >= kMaxDevices) {
     *msg = "no such HIP device";
     return FISH_ERR_ARG;
   }
