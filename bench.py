@@ -664,7 +664,7 @@ def bench_problems(args, torch, fish, fi):
 
 # ------------------------------------------------------------ counter summaries
 # The rocprofv3 counter passes each workload's committed summary comes from
-# (REPO = the repository root on the GPU host; each pass is its own run).
+# (REPO = the repository root, OUT = the output directory; each pass is its own run).
 PMC_PASSES = (
     ("rd", "TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum TCC_EA0_RDREQ_sum"),
     ("wr", "TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum TCC_HIT_sum TCC_MISS_sum"),
@@ -772,11 +772,11 @@ def summarize_counters(workload, outdir, cells, nsteps=2):
     ran = [(sub, c) for sub, c in PMC_PASSES
            if os.path.exists(os.path.join(outdir, f"pmc_{tag}_{sub}", "run_counter_collection.csv"))]
     cmds = ["cd /tmp && export TMPDIR=/tmp"] + [
-        f"rocprofv3 --pmc {c} --output-format csv -d $REPO/gpurun_out/pmc_{tag}_{sub} -o run -- "
+        f"rocprofv3 --pmc {c} --output-format csv -d $OUT/pmc_{tag}_{sub} -o run -- "
         f"python3 $REPO/bench.py {bargs}" for sub, c in ran] + [
-        f"rocprofv3 --pmc {PMC_PASSES[i][1]} --output-format csv -d $REPO/gpurun_out/pmccopy_{PMC_PASSES[i][0]} -o run "
+        f"rocprofv3 --pmc {PMC_PASSES[i][1]} --output-format csv -d $OUT/pmccopy_{PMC_PASSES[i][0]} -o run "
         f"-- python3 $REPO/bench.py {COPY_PROBE}" for i in (0, 1)] + [
-        f"python3 $REPO/bench.py --summarize {workload} --counters-dir $REPO/gpurun_out"]
+        f"python3 $REPO/bench.py --summarize {workload} --counters-dir $OUT"]
     fluid = [n for n in cnt if "fluid_" in n]
     nl = sum(cnt[n] for n in fluid)
     tot_f = sum(_fetch_bytes(agg[n]) for n in fluid)
@@ -804,7 +804,8 @@ def summarize_counters(workload, outdir, cells, nsteps=2):
              "by size" + (f" (a 1 GiB device copy reads {calib['read_GiB_per_copy']:.3f} GiB and writes "
                           f"{calib['write_GiB_per_copy']:.3f} GiB per copy in the same counting)" if calib else "") +
              ".  VALU busy: the kernel's VALU wave-instructions at one per 4 cycles per SIMD (1024 SIMDs, 2.4 GHz)",
-             "over its duration in the sq1 pass.", "", "commands (REPO = the repository root on the GPU host):"] + \
+             "over its duration in the sq1 pass.", "",
+             "commands (REPO = the repository root, OUT = the directory the runs write to):"] + \
         ["  " + c for c in cmds] + ["", f"{'kernel':58s} {'n':>3s} {'dur us':>7s} {'fetch MB':>9s} {'write MB':>9s} "
                                         f"{'algo MB':>8s} {'x algo':>6s} {'TB/s':>5s} {'VALU/cell':>9s} "
                                         f"{'INT32/cell':>10s} {'VALU busy':>9s}"]
@@ -852,10 +853,11 @@ def summarize_trace(tag, outdir):
     tot = sum(sum(v) for v in agg.values())
     span = (int(win[-1]["End_Timestamp"]) - int(win[0]["Start_Timestamp"])) / 1e3
     lines = ["rocprofv3 kernel statistics: " + desc + ".", "",
-             "command (REPO = the repository root on the GPU host):", "  cd /tmp && export TMPDIR=/tmp",
-             f"  rocprofv3 --kernel-trace --stats --output-format csv -d $REPO/gpurun_out/pk_{tag} -o run -- "
+             "command (REPO = the repository root, OUT = the directory the run writes to):",
+             "  cd /tmp && export TMPDIR=/tmp",
+             f"  rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/pk_{tag} -o run -- "
              f"python3 $REPO/bench.py {bargs}",
-             f"  python3 $REPO/bench.py --summarize-trace {tag} --counters-dir $REPO/gpurun_out", "",
+             f"  python3 $REPO/bench.py --summarize-trace {tag} --counters-dir $OUT", "",
              f"{'kernel':66s} {'calls':>5s} {'avg us':>8s} {'min us':>8s} {'max us':>8s} {'%':>6s}"]
     for n, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"{n[:66]:66s} {len(v):5d} {sum(v) / len(v):8.1f} {min(v):8.1f} {max(v):8.1f} "
@@ -919,7 +921,8 @@ def main():
                     help="no run: write the committed counter summary of a workload from its rocprofv3 passes")
     ap.add_argument("--summarize-trace", choices=tuple(TRACED), default=None,
                     help="no run: write the committed kernel-trace summary of a traced run")
-    ap.add_argument("--counters-dir", default=os.path.join(ROOT, "gpurun_out"))
+    ap.add_argument("--counters-dir", default=os.path.join(ROOT, "rocprof_out"),
+                    help="the directory the rocprofv3 runs of --summarize / --summarize-trace wrote to")
     args = ap.parse_args()
     if args.summarize_trace:
         return summarize_trace(args.summarize_trace, args.counters_dir)

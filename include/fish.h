@@ -51,7 +51,7 @@ typedef enum fish_status {
   FISH_ERR_NOMEM = 2,       /* device or host allocation failed             */
   FISH_ERR_DEVICE = 3,      /* a HIP runtime call or kernel launch failed   */
   FISH_ERR_STATE = 4,       /* rho <= 0, p <= 0 or a non-finite value       */
-  FISH_ERR_UNSUPPORTED = 5  /* valid request this build does not implement  */
+  FISH_ERR_UNSUPPORTED = 5  /* valid request the library does not implement */
 } fish_status;
 
 enum { FISH_PERIODIC = 0, FISH_OUTFLOW = 1 };
