@@ -230,6 +230,14 @@ int fish_set_shape(fish_ctx* ctx, int kind, int32_t value);
  * Synchronous; the caller owns out128. */
 int fish_selftest_lane_shift(int device, float* out128);
 
+/* Self-test of the FP64 reciprocal and square root the FP64 sweeps compute
+ * with (no context): hardware estimates refined by Newton steps (1/x) and
+ * Goldschmidt steps (sqrt x), in place of the IEEE division and square-root
+ * sequences.  For the n host values x: rcp_out[i] = 1/x[i] and sqrt_out[i] =
+ * sqrt(x[i]) as the kernels form them.  1 <= n <= 2^24, else FISH_ERR_ARG;
+ * synchronous; the caller owns the three host arrays. */
+int fish_selftest_math(int device, int n, const double* x, double* rcp_out, double* sqrt_out);
+
 /* ------------------------------------------------------------------------
  * Allocation-free double step, for callers that cannot allocate device
  * memory: code under HIP graph capture, tight serving loops, harnesses that

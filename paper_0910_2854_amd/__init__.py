@@ -102,7 +102,7 @@ class Request(ctypes.Structure):
 
 EXPORTS = ("fish_create", "fish_destroy", "fish_last_error", "fish_set_state", "fish_get_state",
            "fish_cfl_dt", "fish_strang_step", "fish_sweep", "fish_diagnostics", "fish_device_bytes",
-           "fish_timing_enable", "fish_timing_read", "fish_selftest_lane_shift", "fish_autotune",
+           "fish_timing_enable", "fish_timing_read", "fish_selftest_lane_shift", "fish_selftest_math", "fish_autotune",
            "fish_box_pool_bytes", "fish_batch_create", "fish_batch_destroy", "fish_batch_last_error",
            "fish_batch_device_bytes", "fish_batch_free_bytes", "fish_batch_count", "fish_batch_add",
            "fish_batch_remove", "fish_batch_get", "fish_batch_box_info", "fish_batch_box_steps", "fish_batch_step",
@@ -181,6 +181,8 @@ def load_library(path: str = LIB_PATH):
     lib.fish_timing_read.argtypes = [vp, P(ctypes.c_int), P(d)]
     lib.fish_selftest_lane_shift.argtypes = [ctypes.c_int, P(ctypes.c_float)]
     lib.fish_selftest_lane_shift.restype = ctypes.c_int
+    lib.fish_selftest_math.argtypes = [ctypes.c_int, ctypes.c_int, P(d), P(d), P(d)]
+    lib.fish_selftest_math.restype = ctypes.c_int
     i32p = P(ctypes.c_int32)
     lib.fish_autotune.argtypes = [vp, ctypes.c_int, i32p]
     lib.fish_box_pool_bytes.argtypes = [P(BoxGeom), ctypes.c_int, ctypes.c_int]
@@ -319,6 +321,19 @@ def selftest_lane_shift(device=0):
     if rc != FISH_OK:
         raise FishError(rc, "lane-shift self-test failed to run")
     return out
+
+
+def selftest_math(x, device=0):
+    """Run the FP64 reciprocal/square-root self-test kernel on the values x;
+    returns (1/x, sqrt(x)) as the FP64 sweeps compute them."""
+    lib = load_library()
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    r = np.empty_like(x)
+    s = np.empty_like(x)
+    rc = lib.fish_selftest_math(int(device), int(x.size), _dptr(x), _dptr(r), _dptr(s))
+    if rc != FISH_OK:
+        raise FishError(rc, "FP64 math self-test failed to run")
+    return r, s
 
 
 def _dptr(a):

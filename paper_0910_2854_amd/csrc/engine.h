@@ -214,4 +214,8 @@ class Engine {
 // Run the lane-shift self-test kernel on `device` (out128: host, 128 values).
 int selftest_lane_shift(int device, float* out128);
 
+// Run the FP64 reciprocal/square-root self-test kernel on `device` (host
+// arrays of n values, 1 <= n <= 2^24).
+int selftest_math(int device, int n, const double* x, double* rcp_out, double* sqrt_out);
+
 }  // namespace fish

@@ -1277,4 +1277,21 @@ int selftest_lane_shift(int device, float* out128) {
   return e == hipSuccess ? 0 : 3;
 }
 
+int selftest_math(int device, int n, const double* x, double* rcp_out, double* sqrt_out) {
+  if (hipSetDevice(device) != hipSuccess) return 3;
+  const size_t bytes = (size_t)n * sizeof(double);
+  double* d = nullptr;
+  if (hipMalloc(&d, 3 * bytes) != hipSuccess) return 2;
+  hipError_t e = hipMemcpy(d, x, bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(math_selftest_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, nullptr, d, d + n,
+                       d + 2 * (size_t)n, n);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(rcp_out, d + n, bytes, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(sqrt_out, d + 2 * (size_t)n, bytes, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  return e == hipSuccess ? 0 : 3;
+}
+
 }  // namespace fish

@@ -319,6 +319,11 @@ int fish_selftest_lane_shift(int device, float* out128) {
   return fish::selftest_lane_shift(device, out128);
 }
 
+int fish_selftest_math(int device, int n, const double* x, double* rcp_out, double* sqrt_out) {
+  if (!x || !rcp_out || !sqrt_out || n < 1 || n > (1 << 24)) return FISH_ERR_ARG;
+  return fish::selftest_math(device, n, x, rcp_out, sqrt_out);
+}
+
 // ------------------------------------------------------------ batch
 size_t fish_box_pool_bytes(const fish_box* b, int precision, int gravity) {
   if (!b) return 0;

@@ -4,8 +4,10 @@
 // that every component index is a compile-time constant (no scratch).
 //
 // FP32 arithmetic uses the hardware reciprocal and square root (1 ulp) in
-// place of the IEEE division/square-root sequences; FP64 arithmetic uses one
-// IEEE reciprocal of the density per cell and multiplies.
+// place of the IEEE division/square-root sequences; FP64 arithmetic refines
+// the hardware estimates by Newton (reciprocal) and Goldschmidt (square root)
+// steps, without the IEEE sequences' range scaling and special-case fixups,
+// and divides by multiplying with the reciprocal.
 //
 // Sect. 2.1-2.4 of the FISH paper; equation numbers are the printed ones.
 #pragma once
@@ -25,14 +27,45 @@ namespace fish {
 enum { RHO = 0, MX = 1, MY = 2, MZ = 3, EN = 4 };
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 
-// 1/rho in FP64 for the pressure recovery: exact division in FP64 mode; in
-// FP32 mode the hardware reciprocal refined by one Newton step in FP64
-// (relative error ~1e-14, far below the FP32 storage rounding of E).
-__device__ __forceinline__ double rinv64(double rho, double) { return 1.0 / rho; }
+// 1/x in FP64: the hardware estimate (relative error about 5e-8) and two
+// Newton steps r <- r + r (1 - x r), each squaring the relative error.  Equal
+// to the IEEE quotient on every sampled finite nonzero x; 0 and infinite x
+// give NaN (the sweeps take reciprocals of densities, cell widths and sums of
+// same-signed slopes, which are positive and finite in any valid state).
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// sqrt(x) in FP64: Goldschmidt's iteration from the hardware estimate y of
+// 1/sqrt(x), carrying s -> sqrt(x) and h -> 1/(2 sqrt(x)) (s = x y, h = y/2),
+// one coupled step and two residual corrections s += h (x - s^2).  Equal to
+// the IEEE root on every sampled positive finite x; sqrt(0) = 0, negative x
+// gives NaN, +inf gives NaN (IEEE: inf), so a non-finite or negative
+// argument still leaves a non-finite result.
+__device__ __forceinline__ double fsqrt(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = 0.5 * y;
+  const double e = fma(-h, s, 0.5);
+  s = fma(s, e, s);
+  h = fma(h, e, h);
+  double d = fma(-s, s, x);
+  s = fma(d, h, s);
+  d = fma(-s, s, x);
+  s = fma(d, h, s);
+  return x == 0.0 ? x : s;
+}
+
+// 1/rho in FP64 for the pressure recovery: the FP64 reciprocal above in FP64
+// mode (the same value as the sweep's 1/rho); in FP32 mode the hardware
+// FP32 reciprocal refined by one Newton step in FP64 (relative error ~1e-14,
+// far below the FP32 storage rounding of E).
+__device__ __forceinline__ double rinv64(double rho, double) { return rcp(rho); }
 __device__ __forceinline__ double rinv64(double rho, float rho32) {
   const double r0 = (double)__builtin_amdgcn_rcpf(rho32);
   return r0 * (2.0 - rho * r0);
@@ -110,8 +143,11 @@ __device__ __forceinline__ T minmod(T a, T b) {
 }
 template <typename T>
 __device__ __forceinline__ T vanleer(T a, T b) {
+  // the quotient is formed unconditionally and selected: as an arm of the
+  // conditional, the FP64 reciprocal's length would keep it a branch
   const T ab = a * b;
-  return ab > T(0) ? T(2) * ab * rcp(a + b) : T(0);
+  const T q = T(2) * ab * rcp(a + b);
+  return ab > T(0) ? q : T(0);
 }
 template <typename T, int LIM>
 __device__ __forceinline__ T limit(T a, T b) {

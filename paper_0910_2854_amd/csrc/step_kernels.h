@@ -1,6 +1,7 @@
 // step_kernels.h -- the small kernels of the engine: per-box step scalars
 // (CFL step, time, status), the fixed-order FP64 diagnostics and the
-// lane-shift self-test.  Included by engine.hip only.
+// self-tests of the lane shift and of the FP64 reciprocal and square root.
+// Included by engine.hip only.
 #pragma once
 
 #include "sweeps.h"
@@ -216,6 +217,16 @@ __global__ void lane_shift_selftest_kernel(float* out) {
   for (int it = 0; it < 2; ++it) {
     const float cur = (float)(100 * it + lane);
     out[64 * it + lane] = lane_shr(cur);
+  }
+}
+
+// Self-test of the FP64 reciprocal and square root the sweeps use:
+// r[i] = rcp(x[i]), s[i] = fsqrt(x[i]) for i < n.
+__global__ void math_selftest_kernel(const double* x, double* r, double* s, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    r[i] = rcp(x[i]);
+    s[i] = fsqrt(x[i]);
   }
 }
 

@@ -634,8 +634,9 @@ __global__ __launch_bounds__(256) void fluid_strided_kernel(FluidLaunch<T> L) {
   // positions s0-3 .. s1+2, padded to an even count (the pad writes nothing;
   // the prefetch reads at most two positions past the end, mapped in range)
   const int npos = (s1 - s0) + 6;
-  if (sizeof(T) == 8) {
-    // FP64: no lookahead; its registers would halve the waves per SIMD
+  if (sizeof(T) == 8 && (GRAV != 0 || HSE || NU || LIM == 2)) {
+    // FP64 with gravity, HSE, an irregular mesh or the limiter switch: no
+    // lookahead; its registers would halve the waves per SIMD (to one)
     for (int it = 0; it < npos; it += 2) {
       compute(it, load(it), hA, hB);
       compute(it + 1, load(it + 1), hB, hA);

@@ -87,6 +87,48 @@ def test_lane_shift_primitive():
     np.testing.assert_array_equal(out, expect)
 
 
+def _ulps(a, b):
+    """Distance in units in the last place between float64 arrays of one sign."""
+    ia = a.view(np.int64).astype(object)
+    ib = b.view(np.int64).astype(object)
+    return np.array([abs(p - q) for p, q in zip(ia, ib)], dtype=np.float64)
+
+
+def test_fp64_reciprocal_and_square_root():
+    """The FP64 sweeps form 1/x and sqrt(x) from the hardware estimates with
+    Newton and Goldschmidt steps instead of the IEEE sequences.  Against
+    numpy's IEEE division and square root: within one ulp (in practice equal)
+    wherever the argument and the result are normal numbers, sqrt(0) = 0 with
+    its sign, NaN for a negative root; the special inputs the sweeps never
+    pass (0 and infinity for 1/x, infinity for the root) give NaN."""
+    import paper_0910_2854_amd as fish
+    print("FP64 reciprocal / square-root self-test", flush=True)
+    rng = np.random.default_rng(11)
+    n = 1 << 18
+    e = rng.integers(-1021, 1021, n)
+    x = np.ldexp(rng.uniform(1.0, 2.0, n), e) * np.where(rng.integers(0, 2, n) == 1, 1.0, -1.0)
+    x[:8] = [1.0, -1.0, 3.0, 0.1, 1e-300, 1e300, 2.0 ** -1021, 1.5 * 2.0 ** 1020]
+    r, s = fish.selftest_math(x)
+    with np.errstate(invalid="ignore"):
+        ref_r = 1.0 / x
+        pos = x > 0
+        ref_s = np.sqrt(np.where(pos, x, 1.0))
+    ur = _ulps(r, ref_r)
+    us = _ulps(s[pos], ref_s[pos])
+    print(f"  1/x: max {ur.max():.0f} ulp, {int(np.count_nonzero(ur))} of {n} differ; "
+          f"sqrt: max {us.max():.0f} ulp, {int(np.count_nonzero(us))} of {int(pos.sum())} differ", flush=True)
+    assert ur.max() <= 1 and us.max() <= 1
+    assert np.all(np.isnan(s[~pos]))
+    special = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, 2.0 ** -1074, 2.0 ** -1030, 2.0 ** 1023])
+    r, s = fish.selftest_math(special)
+    print("  special x:", special.tolist(), flush=True)
+    print("  1/x:", r.tolist(), flush=True)
+    print("  sqrt:", s.tolist(), flush=True)
+    assert s[0] == 0.0 and not np.signbit(s[0]) and s[1] == 0.0 and np.signbit(s[1])
+    assert np.isnan(r[0]) and np.isnan(r[1]) and np.isnan(r[2]) and np.isnan(r[3]) and np.isnan(r[4])
+    assert np.isnan(s[2]) and np.isnan(s[3]) and np.isnan(s[4])
+
+
 # van Leer and the Mach switch on every shape, minmod on a subset
 LIMITER_CASES = [(c, lim) for lim in (1, 2) for c in range(len(CASES))] + [(c, 0) for c in (0, 3, 5, 10)]
 
