@@ -87,6 +87,10 @@ class Engine {
   // sweep takes per-cell widths
   DeviceBuf wid[3];
   bool nonuniform = false;
+  // axes along which every table box has one cell: the fluid sweep there is
+  // the identity (every ghost is the cell itself, so every flux difference
+  // and every potential difference is zero) and is not launched
+  bool flat[3] = {false, false, false};
   int cur[8]{};
   std::map<long long, long long> free_list;  // offset -> length (elements)
 

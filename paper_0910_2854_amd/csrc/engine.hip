@@ -718,6 +718,10 @@ int Engine::build_lists() {
   if (anynu && (rc = esize == 8 ? upload_widths<double>(slots, wtotal) : upload_widths<float>(slots, wtotal)))
     return rc;
   nonuniform = anynu;
+  for (int a = 0; a < 3; ++a) {
+    flat[a] = nb > 0;
+    for (int s : slots) flat[a] = flat[a] && boxes[s].n[a] == 1;
+  }
   // the spare set is written once every launch that read it has completed
   HIP_TRY(hipEventSynchronize(spare.done));
   drop_retired_graphs();

@@ -31,9 +31,10 @@ __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(
 
 // 1/x in FP64: the hardware estimate (relative error about 5e-8) and two
 // Newton steps r <- r + r (1 - x r), each squaring the relative error.  Equal
-// to the IEEE quotient on every sampled finite nonzero x; 0 and infinite x
-// give NaN (the sweeps take reciprocals of densities, cell widths and sums of
-// same-signed slopes, which are positive and finite in any valid state).
+// to the IEEE quotient on every sampled x whose reciprocal is a finite
+// nonzero number; 0, infinite x and an overflowing reciprocal give NaN (the
+// sweeps take reciprocals of densities, cell widths and sums of same-signed
+// slopes, which are positive and finite in any valid state).
 __device__ __forceinline__ double rcp(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
@@ -44,10 +45,11 @@ __device__ __forceinline__ double rcp(double x) {
 
 // sqrt(x) in FP64: Goldschmidt's iteration from the hardware estimate y of
 // 1/sqrt(x), carrying s -> sqrt(x) and h -> 1/(2 sqrt(x)) (s = x y, h = y/2),
-// one coupled step and two residual corrections s += h (x - s^2).  Equal to
-// the IEEE root on every sampled positive finite x; sqrt(0) = 0, negative x
-// gives NaN, +inf gives NaN (IEEE: inf), so a non-finite or negative
-// argument still leaves a non-finite result.
+// one coupled step and two residual corrections s += h (x - s^2).  Within one
+// ulp of the IEEE root for positive finite x, subnormals included (equal on
+// nearly every sample); sqrt(0) = 0, negative x gives NaN, +inf gives NaN
+// (IEEE: inf), so a non-finite or negative argument still leaves a
+// non-finite result.
 __device__ __forceinline__ double fsqrt(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   double s = x * y, h = 0.5 * y;
