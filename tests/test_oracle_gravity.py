@@ -93,7 +93,10 @@ def _hydrostatic_pencil(n, dphi, rho0=1.0, p0=1.0):
             f = dphi / (c0 * c1)
             return [r1 - r0 + 0.5 * (r0 + r1) * f, E1 - E0 + 0.5 * (E0 + q0 + E1 + q1) * f]
 
-        sol = optimize.fsolve(res, [r0, q0], xtol=1e-13)
+        # solved to rounding: fsolve may then report slow progress, so the
+        # residual itself is checked instead of its status
+        sol, _, _, _ = optimize.fsolve(res, [r0, q0], xtol=1e-13, full_output=True)
+        assert np.max(np.abs(res(sol))) <= 1e-14 * max(r0, E0), res(sol)
         rho.append(sol[0])
         p.append(sol[1])
     return np.array(rho), np.array(p)
