@@ -3,8 +3,8 @@ context's fish_strang_step on the same state: both run the same kernels on
 the same inputs, so the states after the step, the step size and the CFL
 step of the new state must agree bitwise.  Two calls in a row on one GPU,
 the second on a smaller box, so that it runs on the scratch the first call
-left behind (in FP32 a third on a flat box, whose z fluid sweeps both leave
-out); in FP64 and FP32, with the CFL step (dt = 0) and a given dt,
+left behind (a third call in each precision: split gravity with HSE in FP64,
+a flat box, whose z fluid sweeps both leave out, in FP32); in FP64 and FP32, with the CFL step (dt = 0) and a given dt,
 with and without gravity and the hydrostatic correction.  Device arrays come
 from torch and the work is enqueued on torch's current stream."""
 
@@ -81,7 +81,8 @@ def _noalloc_step(fish, n, bc, st, precision, dt, **kw):
 # (shape, bc, gravity, hse, dt mode, seed): two calls in a row per case, the second smaller
 CALLS = {
     "fp64": [((40, 36, 44), (P, P, P), False, False, "cfl", 11),
-             ((20, 12, 16), (O, P, O), True, True, "given", 12)],
+             ((20, 12, 16), (O, P, O), True, True, "given", 12),
+             ((16, 14, 12), (O, O, O), "split", True, "cfl", 13)],
     "fp32": [((48, 32, 40), (O, O, O), True, False, "given", 21),
              ((12, 10, 8), (P, P, P), False, False, "cfl", 22),
              ((24, 20, 1), (P, P, P), False, False, "cfl", 23)],
