@@ -1,12 +1,13 @@
 """The allocation-free double step (fish_strang_step_noalloc) against the
 context's fish_strang_step on the same state: both run the same kernels on
 the same inputs, so the states after the step, the step size and the CFL
-step of the new state must agree bitwise.  Two calls in a row on one GPU,
-the second on a smaller box, so that it runs on the scratch the first call
-left behind (a third call in each precision: split gravity with HSE in FP64,
-a flat box, whose z fluid sweeps both leave out, in FP32); in FP64 and FP32, with the CFL step (dt = 0) and a given dt,
-with and without gravity and the hydrostatic correction.  Device arrays come
-from torch and the work is enqueued on torch's current stream."""
+step of the new state must agree bitwise.  Three calls in a row on one GPU
+per precision, each on a smaller box than the one before, so that each runs
+on the scratch the previous call left behind: in FP64 and FP32, with the CFL
+step (dt = 0) and a given dt, without gravity, with unsplit gravity and the
+hydrostatic correction, with split gravity (FP64) and on a flat box, whose
+z fluid sweeps both leave out (FP32).  Device arrays come from torch and the
+work is enqueued on torch's current stream."""
 
 import numpy as np
 import pytest
@@ -78,7 +79,7 @@ def _noalloc_step(fish, n, bc, st, precision, dt, **kw):
     return out, rep
 
 
-# (shape, bc, gravity, hse, dt mode, seed): two calls in a row per case, the second smaller
+# (shape, bc, gravity, hse, dt mode, seed): successive calls, each on a smaller box
 CALLS = {
     "fp64": [((40, 36, 44), (P, P, P), False, False, "cfl", 11),
              ((20, 12, 16), (O, P, O), True, True, "given", 12),
@@ -90,7 +91,7 @@ CALLS = {
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_noalloc_step_equals_the_context_step_on_two_calls_in_a_row(precision):
+def test_noalloc_step_equals_the_context_step_on_successive_calls(precision):
     import paper_0910_2854_amd as fish
     for n, bc, grav, hse, mode, seed in CALLS[precision]:
         print(f"noalloc {precision} shape {n} bc {bc} gravity {grav} hse {hse} dt {mode} seed {seed}", flush=True)
