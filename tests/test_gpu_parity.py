@@ -98,9 +98,10 @@ def test_fp64_reciprocal_and_square_root():
     """The FP64 sweeps form 1/x and sqrt(x) from the hardware estimates with
     Newton and Goldschmidt steps instead of the IEEE sequences.  Against
     numpy's IEEE division and square root: within one ulp (in practice equal)
-    wherever the argument and the result are normal numbers, sqrt(0) = 0 with
-    its sign, NaN for a negative root; the special inputs the sweeps never
-    pass (0 and infinity for 1/x, infinity for the root) give NaN."""
+    wherever the argument and the result are normal numbers, and for the roots
+    of subnormal numbers; sqrt(0) = 0 with its sign, NaN for a negative root;
+    the special inputs the sweeps never pass (0, infinity and subnormal x for
+    1/x, infinity for the root) give NaN."""
     import paper_0910_2854_amd as fish
     print("FP64 reciprocal / square-root self-test", flush=True)
     rng = np.random.default_rng(11)
@@ -127,6 +128,10 @@ def test_fp64_reciprocal_and_square_root():
     assert s[0] == 0.0 and not np.signbit(s[0]) and s[1] == 0.0 and np.signbit(s[1])
     assert np.isnan(r[0]) and np.isnan(r[1]) and np.isnan(r[2]) and np.isnan(r[3]) and np.isnan(r[4])
     assert np.isnan(s[2]) and np.isnan(s[3]) and np.isnan(s[4])
+    # subnormal arguments: their reciprocals overflow (NaN here, IEEE infinity);
+    # their roots, and both results for the largest binade, are right
+    assert np.isnan(r[5]) and np.isnan(r[6]) and r[7] == 1.0 / special[7]
+    assert _ulps(s[5:], np.sqrt(special[5:])).max() <= 1
 
 
 # van Leer and the Mach switch on every shape, minmod on a subset
